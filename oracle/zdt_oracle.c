@@ -1,0 +1,259 @@
+/*
+ * zdt_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, single-threaded CPU statement of what the stereo hot path
+ * computes: ZNCC matching cost (Sec. III-A), domain-transform aggregation
+ * (Sec. III-B, Eqs. DT1-DT4 with the weights of Eqs. k1-k4 and a), and
+ * winner-take-all (Sec. III-C, Eq. WTA1).  Integers are int64, floating point
+ * is IEEE double.  It shares no source, header or table with the HIP library;
+ * only the tests, the smoke check and the benchmark's CPU-baseline leg may
+ * load it.
+ *
+ * Readings taken where the paper is silent or loose (each also listed in the
+ * design notes of the repository):
+ *   - left image = reference I_R, right image = target I_T, candidate I_T(x-d,y),
+ *     d in [0, D) (Sec. III-A).
+ *   - every pixel read is clamped to the image (replicate border), including
+ *     target columns x-d+i < 0; the target window sums live on the extended
+ *     column domain x' in [-(D-1), W-1].
+ *   - a window of zero variance (exact integer test) gives ZNCC = 0, cost 1.
+ *   - ZNCC is clamped to [-1, 1] (the text prints [0,1]; Cauchy-Schwarz gives
+ *     [-1,1]); the aggregated quantity is the cost 1 - ZNCC and WTA takes its
+ *     argmin, lowest d on ties (Eq. WTA1).
+ *   - the DT weights come from the reference (left) image unless the caller
+ *     asks for the target; intensity differences are in 0..255 units and
+ *     sigma_r is given in intensity/255 units, so the exponent is
+ *     -1/sigma_s - |dI| / (255 sigma_r)  (Eq. weight, a = exp(-1/sigma_s)).
+ *   - W_R(x) = W_L(x+1) and W_D(y) = W_U(y+1) (Eqs. k1-k4); boundaries
+ *     C_L(0)=C(0), C_R(W-1)=C_L(W-1), C_U(.,0)=C_R(.,0), C_D(.,H-1)=C_U(.,H-1).
+ *   - "iterations": one L,R,U,D sweep is the paper's DT; I > 1 repeats the same
+ *     four passes with the same weights on the previous sweep's output.
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+/* I(u, v) with the replicate-border reading. */
+static int pix(const uint8_t* img, int pitch, int W, int H, int u, int v) {
+  return img[(ptrdiff_t)clampi(v, 0, H - 1) * pitch + clampi(u, 0, W - 1)];
+}
+
+/* ---------------------------------------------------------------------------
+ * Window sums over the (2r+1)x(2r+1) window W centred on a pixel (Sec. IV-B,
+ * Eq. sum1: S = sum of the pixel values of the window, computed directly).
+ * S_L, S_LL : reference sums of I and I^2 at (x, y), arrays [H][W].
+ * S_T, S_TT : target sums at (x', y) for x' in [-(D-1), W-1], arrays
+ *             [H][W + D - 1] indexed by x' + D - 1.
+ * ------------------------------------------------------------------------- */
+int oracle_window_sums(const uint8_t* L, const uint8_t* R, int pitch, int W, int H, int D, int r,
+                       int64_t* S_L, int64_t* S_LL, int64_t* S_T, int64_t* S_TT) {
+  if (W < 1 || H < 1 || D < 1 || r < 0 || pitch < W) return -1;
+  const int WE = W + D - 1;
+  for (int y = 0; y < H; ++y) {
+    for (int x = 0; x < W; ++x) {
+      int64_t s = 0, ss = 0;
+      for (int j = -r; j <= r; ++j)
+        for (int i = -r; i <= r; ++i) {
+          int64_t v = pix(L, pitch, W, H, x + i, y + j);
+          s += v;
+          ss += v * v;
+        }
+      S_L[(ptrdiff_t)y * W + x] = s;
+      S_LL[(ptrdiff_t)y * W + x] = ss;
+    }
+    for (int xe = -(D - 1); xe < W; ++xe) {
+      int64_t s = 0, ss = 0;
+      for (int j = -r; j <= r; ++j)
+        for (int i = -r; i <= r; ++i) {
+          int64_t v = pix(R, pitch, W, H, xe + i, y + j);
+          s += v;
+          ss += v * v;
+        }
+      S_T[(ptrdiff_t)y * WE + xe + D - 1] = s;
+      S_TT[(ptrdiff_t)y * WE + xe + D - 1] = ss;
+    }
+  }
+  return 0;
+}
+
+/* Cross sum  S_RT(x,y,d) = sum over the window of I_R(x+i,y+j) * I_T(x-d+i,y+j)
+ * (the Pi_RT term of Eq. OP_ZNCC), brute force, array [H][W][D]. */
+int oracle_cross_sums(const uint8_t* L, const uint8_t* R, int pitch, int W, int H, int D, int r,
+                      int64_t* S_RT) {
+  if (W < 1 || H < 1 || D < 1 || r < 0 || pitch < W) return -1;
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x)
+      for (int d = 0; d < D; ++d) {
+        int64_t s = 0;
+        for (int j = -r; j <= r; ++j)
+          for (int i = -r; i <= r; ++i)
+            s += (int64_t)pix(L, pitch, W, H, x + i, y + j) * pix(R, pitch, W, H, x - d + i, y + j);
+        S_RT[((ptrdiff_t)y * W + x) * D + d] = s;
+      }
+  return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * ZNCC by its defining formula (Eq. ZNCC): deviations from the window means,
+ * their cross sum over the standard deviations.  Returns z in [-1, 1].
+ * Zero variance (exact integer test on l^2*sum(I^2) - (sum I)^2) gives z = 0.
+ * ------------------------------------------------------------------------- */
+double oracle_zncc_at(const uint8_t* L, const uint8_t* R, int pitch, int W, int H, int r, int x, int y,
+                      int d) {
+  const int l = 2 * r + 1;
+  const double N = (double)l * l;
+  int64_t sl = 0, sll = 0, st = 0, stt = 0;
+  for (int j = -r; j <= r; ++j)
+    for (int i = -r; i <= r; ++i) {
+      int64_t a = pix(L, pitch, W, H, x + i, y + j);
+      int64_t b = pix(R, pitch, W, H, x - d + i, y + j);
+      sl += a;
+      sll += a * a;
+      st += b;
+      stt += b * b;
+    }
+  const int64_t NL = (int64_t)l * l;
+  if (NL * sll - sl * sl == 0 || NL * stt - st * st == 0) return 0.0;
+  const double mean_r = (double)sl / N, mean_t = (double)st / N;
+  double num = 0.0, var_r = 0.0, var_t = 0.0;
+  for (int j = -r; j <= r; ++j)
+    for (int i = -r; i <= r; ++i) {
+      double dr = pix(L, pitch, W, H, x + i, y + j) - mean_r;
+      double dt = pix(R, pitch, W, H, x - d + i, y + j) - mean_t;
+      num += dr * dt;
+      var_r += dr * dr;
+      var_t += dt * dt;
+    }
+  double z = num / (sqrt(var_r) * sqrt(var_t));
+  if (z > 1.0) z = 1.0;
+  if (z < -1.0) z = -1.0;
+  return z;
+}
+
+/* Matching cost 1 - ZNCC for one disparity slice d, array [H][W]. */
+int oracle_zncc_cost_slice(const uint8_t* L, const uint8_t* R, int pitch, int W, int H, int r, int d,
+                           double* cost_hw) {
+  if (W < 1 || H < 1 || r < 0 || d < 0 || pitch < W) return -1;
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x)
+      cost_hw[(ptrdiff_t)y * W + x] = 1.0 - oracle_zncc_at(L, R, pitch, W, H, r, x, y, d);
+  return 0;
+}
+
+/* Matching cost 1 - ZNCC for the whole volume, array [H][W][D]. */
+int oracle_zncc_cost(const uint8_t* L, const uint8_t* R, int pitch, int W, int H, int D, int r,
+                     double* cost_hwd) {
+  if (W < 1 || H < 1 || D < 1 || r < 0 || pitch < W) return -1;
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x)
+      for (int d = 0; d < D; ++d)
+        cost_hwd[((ptrdiff_t)y * W + x) * D + d] = 1.0 - oracle_zncc_at(L, R, pitch, W, H, r, x, y, d);
+  return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * DT edge weights (Eqs. k1-k4, a, weight):
+ *   wh[y][x] = W_L(x,y) = exp(-1/sigma_s - |G(x,y) - G(x-1,y)| / (255 sigma_r)),  x >= 1
+ *   wv[y][x] = W_U(x,y) = exp(-1/sigma_s - |G(x,y) - G(x,y-1)| / (255 sigma_r)),  y >= 1
+ * wh[y][0] = wv[0][x] = 0 (no neighbour).  sigma_r = +inf disables the range term.
+ * ------------------------------------------------------------------------- */
+int oracle_dt_weights(const uint8_t* G, int pitch, int W, int H, double sigma_s, double sigma_r, double* wh,
+                      double* wv) {
+  if (W < 1 || H < 1 || !(sigma_s > 0.0) || !(sigma_r > 0.0) || pitch < W) return -1;
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x) {
+      const int g = G[(ptrdiff_t)y * pitch + x];
+      double h = 0.0, v = 0.0;
+      if (x >= 1) h = exp(-1.0 / sigma_s - fabs((double)(g - G[(ptrdiff_t)y * pitch + x - 1])) / (255.0 * sigma_r));
+      if (y >= 1) v = exp(-1.0 / sigma_s - fabs((double)(g - G[(ptrdiff_t)(y - 1) * pitch + x])) / (255.0 * sigma_r));
+      wh[(ptrdiff_t)y * W + x] = h;
+      wv[(ptrdiff_t)y * W + x] = v;
+    }
+  return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * DT recursions (Eqs. DT1-DT4), evaluated literally and in place on one
+ * disparity slice whose element (x, y) sits at c[y*sy + x*sx]:
+ *   L: C_L(x) = C(x)   + W_L(x) C_L(x-1)      x = 1 .. W-1
+ *   R: C_R(x) = C_L(x) + W_R(x) C_R(x+1)      x = W-2 .. 0,  W_R(x) = wh(x+1)
+ *   U: C_U(y) = C_R(y) + W_U(y) C_U(y-1)      y = 1 .. H-1
+ *   D: C_D(y) = C_U(y) + W_D(y) C_D(y+1)      y = H-2 .. 0,  W_D(y) = wv(y+1)
+ * repeated `iters` times; C is replaced by C_D after each sweep (Sec. III-B).
+ * ------------------------------------------------------------------------- */
+static void dt_slice_strided(double* c, ptrdiff_t sx, ptrdiff_t sy, int W, int H, const double* wh,
+                             const double* wv, int iters) {
+  for (int it = 0; it < iters; ++it) {
+    for (int y = 0; y < H; ++y)
+      for (int x = 1; x < W; ++x)
+        c[y * sy + x * sx] += wh[(ptrdiff_t)y * W + x] * c[y * sy + (x - 1) * sx];
+    for (int y = 0; y < H; ++y)
+      for (int x = W - 2; x >= 0; --x)
+        c[y * sy + x * sx] += wh[(ptrdiff_t)y * W + x + 1] * c[y * sy + (x + 1) * sx];
+    for (int x = 0; x < W; ++x)
+      for (int y = 1; y < H; ++y)
+        c[y * sy + x * sx] += wv[(ptrdiff_t)y * W + x] * c[(y - 1) * sy + x * sx];
+    for (int x = 0; x < W; ++x)
+      for (int y = H - 2; y >= 0; --y)
+        c[y * sy + x * sx] += wv[(ptrdiff_t)(y + 1) * W + x] * c[(y + 1) * sy + x * sx];
+  }
+}
+
+/* One disparity slice, array [H][W], aggregated in place. */
+int oracle_dt_slice(double* c_hw, int W, int H, const double* wh, const double* wv, int iters) {
+  if (W < 1 || H < 1 || iters < 0) return -1;
+  dt_slice_strided(c_hw, 1, W, W, H, wh, wv, iters);
+  return 0;
+}
+
+/* Whole volume [H][W][D] aggregated in place, slice by slice. */
+int oracle_dt_aggregate(double* vol_hwd, int W, int H, int D, const double* wh, const double* wv, int iters) {
+  if (W < 1 || H < 1 || D < 1 || iters < 0) return -1;
+  for (int d = 0; d < D; ++d) dt_slice_strided(vol_hwd + d, D, (ptrdiff_t)W * D, W, H, wh, wv, iters);
+  return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * WTA (Eq. WTA1): the smallest d attaining min_d C(x,y,d); vol is [H][W][D].
+ * ------------------------------------------------------------------------- */
+int oracle_wta(const double* vol_hwd, int W, int H, int D, int32_t* disp_hw) {
+  if (W < 1 || H < 1 || D < 1) return -1;
+  for (ptrdiff_t p = 0; p < (ptrdiff_t)W * H; ++p) {
+    const double* c = vol_hwd + p * D;
+    int best = 0;
+    for (int d = 1; d < D; ++d)
+      if (c[d] < c[best]) best = d;
+    disp_hw[p] = best;
+  }
+  return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * The whole path: cost 1 - ZNCC, DT with guide = reference (or target when
+ * guide_target != 0), WTA.  cost_agg_hwd (nullable) receives the aggregated
+ * volume; scratch is allocated here with malloc.
+ * ------------------------------------------------------------------------- */
+int oracle_stereo_solve(const uint8_t* L, const uint8_t* R, int pitch, int W, int H, int D, int r,
+                        double sigma_s, double sigma_r, int iters, int guide_target, double* cost_agg_hwd,
+                        int32_t* disp_hw) {
+  if (W < 1 || H < 1 || D < 1 || r < 0 || iters < 0 || pitch < W) return -1;
+  const size_t nv = (size_t)W * H * D, np = (size_t)W * H;
+  double* vol = cost_agg_hwd ? cost_agg_hwd : (double*)malloc(nv * sizeof(double));
+  double* wh = (double*)malloc(np * sizeof(double));
+  double* wv = (double*)malloc(np * sizeof(double));
+  int rc = -2;
+  if (vol && wh && wv) {
+    rc = oracle_zncc_cost(L, R, pitch, W, H, D, r, vol);
+    if (rc == 0) rc = oracle_dt_weights(guide_target ? R : L, pitch, W, H, sigma_s, sigma_r, wh, wv);
+    if (rc == 0) rc = oracle_dt_aggregate(vol, W, H, D, wh, wv, iters);
+    if (rc == 0) rc = oracle_wta(vol, W, H, D, disp_hw);
+  }
+  free(wv);
+  free(wh);
+  if (!cost_agg_hwd) free(vol);
+  return rc;
+}

@@ -1,0 +1,212 @@
+"""Seeded synthetic stereo scenes.
+
+These stand in for the rectified KITTI-2015-sized grayscale pairs the paper
+evaluates on (Sec. V: 1280x384 and ~1242x375, D = 128), which are not
+available here.  A scene is a stack of planar layers rendered exactly into both
+views: layer k has a region on the reference (left) grid, a disparity plane
+d_k(x, y) = a + b x + c y and its own texture.  The left view shows the
+frontmost layer (largest disparity); the right view places each layer's texture
+at x' = x - d_k(x, y), inverted in closed form, with gain, bias and Gaussian
+noise, rounded half-to-even and clipped to 0..255.  Right pixels with no
+preimage get fresh noise.  Ground truth is d_top on the left grid, with a
+validity mask that drops occluded pixels and targets outside the frame.
+
+This module computes no part of the matching method; it only makes inputs.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class StereoPair:
+    left: np.ndarray       # uint8 [H][W], reference image
+    right: np.ndarray      # uint8 [H][W], target image
+    gt: np.ndarray         # float32 [H][W], ground-truth disparity on the left grid
+    valid: np.ndarray      # bool [H][W]
+    max_disp: int
+    seed: int
+
+
+def _box3(img):
+    p = np.pad(img, 1, mode="edge")
+    out = np.zeros_like(img, dtype=np.float64)
+    for j in range(3):
+        for i in range(3):
+            out += p[j:j + img.shape[0], i:i + img.shape[1]]
+    return out / 9.0
+
+
+def _blur(img, passes):
+    for _ in range(passes):
+        img = _box3(img)
+    return img
+
+
+def _octave_texture(rng, H, W, std=40.0):
+    """Multi-octave blurred noise, mean 128, the given standard deviation."""
+    acc = np.zeros((H, W))
+    for k, amp in enumerate((1.0, 0.7, 0.5, 0.35)):
+        step = 2 ** k
+        h, w = (H + step - 1) // step + 2, (W + step - 1) // step + 2
+        n = rng.standard_normal((h, w))
+        n = np.repeat(np.repeat(n, step, axis=0), step, axis=1)[:H, :W]
+        acc += amp * _blur(n, 1 + k // 2)
+    acc = (acc - acc.mean()) / max(acc.std(), 1e-9)
+    return 128.0 + std * acc
+
+
+@dataclass
+class _Layer:
+    a: float
+    b: float
+    c: float
+    tex: np.ndarray        # float64 [H][W+2], sampled at fractional x
+    inside: callable       # (x, y) float arrays -> bool array
+
+
+def _sample(tex, x, y):
+    """Linear interpolation of tex along x at fractional x (integer rows y)."""
+    W = tex.shape[1]
+    x = np.clip(x, 0.0, W - 1.000001)
+    x0 = np.floor(x).astype(np.int64)
+    f = x - x0
+    return tex[y, x0] * (1.0 - f) + tex[y, x0 + 1] * f
+
+
+def _render(layers, H, W, D, rng, gain, bias, noise, seed):
+    ys, xs = np.mgrid[0:H, 0:W].astype(np.float64)
+    yi = ys.astype(np.int64)
+    # left view: frontmost layer on the left grid
+    top = np.full((H, W), -1, np.int64)
+    dtop = np.full((H, W), -np.inf)
+    for k, L in enumerate(layers):
+        dk = L.a + L.b * xs + L.c * ys
+        m = L.inside(xs, ys) & (dk > dtop)
+        top[m] = k
+        dtop[m] = dk[m]
+    left = np.empty((H, W))
+    for k, L in enumerate(layers):
+        m = top == k
+        left[m] = L.tex[yi[m], xs[m].astype(np.int64)]
+    # right view: at x', the layer whose preimage x = (x' + a + c y) / (1 - b) is frontmost
+    rtop = np.full((H, W), -1, np.int64)
+    rd = np.full((H, W), -np.inf)
+    rx = np.zeros((H, W))
+    for k, L in enumerate(layers):
+        x = (xs + L.a + L.c * ys) / (1.0 - L.b)
+        ok = (x >= 0.0) & (x <= W - 1) & L.inside(x, ys)
+        dk = x - xs
+        m = ok & (dk > rd)
+        rtop[m] = k
+        rd[m] = dk[m]
+        rx[m] = x[m]
+    right = rng.uniform(0.0, 255.0, (H, W))
+    for k, L in enumerate(layers):
+        m = rtop == k
+        right[m] = gain * _sample(L.tex, rx[m], yi[m]) + bias
+    right = right + rng.normal(0.0, noise, (H, W))
+    right = np.clip(np.rint(right), 0, 255).astype(np.uint8)
+    left = np.clip(np.rint(left), 0, 255).astype(np.uint8)
+    # validity: target inside the frame, not occluded in the right view, disparity in range
+    xt = xs - dtop
+    valid = (xt >= 0.0) & (dtop >= 0.0) & (dtop <= D - 1)
+    for k, L in enumerate(layers):
+        x = (xt + L.a + L.c * ys) / (1.0 - L.b)
+        occ = (x >= 0.0) & (x <= W - 1) & L.inside(x, ys) & ((x - xt) > dtop + 1e-6) & (top != k)
+        valid &= ~occ
+    return StereoPair(left=left, right=right, gt=dtop.astype(np.float32), valid=valid, max_disp=D, seed=seed)
+
+
+def bands_pair(W=320, H=96, D=32, seed=0, band_disps=(5, 12, 20), gain=0.9, bias=5.0, noise=2.0):
+    """Piecewise-constant disparity: vertical bands of equal width sharing one
+    texture (uniform 0..255 noise, box-blurred 3x3)."""
+    rng = np.random.default_rng(seed)
+    tex = _box3(rng.uniform(0.0, 255.0, (H, W + 2)))
+    n = len(band_disps)
+    edges = [round(i * W / n) for i in range(n + 1)]
+    layers = []
+    for k, d in enumerate(band_disps):
+        lo, hi = edges[k], edges[k + 1]
+        layers.append(_Layer(a=float(d), b=0.0, c=0.0, tex=tex,
+                             inside=(lambda lo, hi: lambda x, y: (x >= lo) & (x < hi))(lo, hi)))
+    pair = _render(layers, H, W, D, rng, gain, bias, noise, seed)
+    pair.band_edges = edges
+    pair.band_disps = tuple(band_disps)
+    return pair
+
+
+def _ellipse(cx, cy, rx, ry):
+    return lambda x, y: ((x - cx) / rx) ** 2 + ((y - cy) / ry) ** 2 <= 1.0
+
+
+def _convex_quad(pts):
+    pts = np.asarray(pts, np.float64)
+    c = pts.mean(axis=0)
+    ang = np.arctan2(pts[:, 1] - c[1], pts[:, 0] - c[0])
+    pts = pts[np.argsort(ang)]
+
+    def inside(x, y):
+        ok = np.ones(np.shape(x), bool)
+        for i in range(4):
+            x0, y0 = pts[i]
+            x1, y1 = pts[(i + 1) % 4]
+            ok &= (x1 - x0) * (y - y0) - (y1 - y0) * (x - x0) >= 0.0
+        return ok
+    return inside
+
+
+def planes_pair(W=1280, H=384, D=128, seed=1, n_planes=None, noise=2.0):
+    """Textured background with a gentle disparity slope in [0, D/8] plus
+    randomly placed slanted planes (ellipses or convex quads), each with its own
+    texture and |b|, |c| <= 0.2, disparity kept inside [0, D-1] over its region;
+    target gain U(0.8, 1.2), bias U(-10, 10), noise sigma 2."""
+    rng = np.random.default_rng(seed)
+    if n_planes is None:
+        n_planes = int(np.clip(round(6 * (W * H) / (1280 * 384)), 2, 24))
+    layers = []
+    dmax_bg = D / 8.0
+    b0 = rng.uniform(0.0, 0.5) * dmax_bg / W
+    c0 = (dmax_bg - b0 * W) / H * rng.uniform(0.3, 1.0)
+    layers.append(_Layer(a=0.0, b=b0, c=c0, tex=_octave_texture(rng, H, W + 2),
+                         inside=lambda x, y: np.ones(np.shape(x), bool)))
+    for _ in range(n_planes):
+        cx, cy = rng.uniform(0.1 * W, 0.9 * W), rng.uniform(0.1 * H, 0.9 * H)
+        sx, sy = rng.uniform(0.05 * W, 0.18 * W), rng.uniform(0.08 * H, 0.3 * H)
+        if rng.uniform() < 0.5:
+            inside = _ellipse(cx, cy, sx, sy)
+            xlo, xhi, ylo, yhi = cx - sx, cx + sx, cy - sy, cy + sy
+        else:
+            ang = np.sort(rng.uniform(0.0, 2.0 * np.pi, 4))
+            pts = np.stack([cx + sx * np.cos(ang), cy + sy * np.sin(ang)], axis=1)
+            inside = _convex_quad(pts)
+            xlo, xhi = pts[:, 0].min(), pts[:, 0].max()
+            ylo, yhi = pts[:, 1].min(), pts[:, 1].max()
+        b, c = rng.uniform(-0.2, 0.2), rng.uniform(-0.2, 0.2)
+        corners = [b * x + c * y for x in (xlo, xhi) for y in (ylo, yhi)]
+        span = max(corners) - min(corners)
+        if span > D - 1:
+            s = (D - 1) / span
+            b, c = b * s, c * s
+            corners = [b * x + c * y for x in (xlo, xhi) for y in (ylo, yhi)]
+        lo, hi = -min(corners), D - 1 - max(corners)
+        a = rng.uniform(min(lo + dmax_bg, hi), hi) if hi > lo else lo
+        layers.append(_Layer(a=a, b=b, c=c, tex=_octave_texture(rng, H, W + 2, std=rng.uniform(25, 50)),
+                             inside=inside))
+    gain, bias = rng.uniform(0.8, 1.2), rng.uniform(-10.0, 10.0)
+    return _render(layers, H, W, D, rng, gain, bias, noise, seed)
+
+
+def workload(name, seed=None):
+    """The named synthetic workloads used by the tests and the benchmark."""
+    if name == "bands_320x96_d32":
+        return bands_pair(seed=0 if seed is None else seed)
+    if name == "planes_1280x384_d128":
+        return planes_pair(1280, 384, 128, seed=1 if seed is None else seed)
+    if name == "planes_640x192_d64":
+        return planes_pair(640, 192, 64, seed=100 if seed is None else seed)
+    if name == "planes_1920x1080_d256":
+        return planes_pair(1920, 1080, 256, seed=100 if seed is None else seed)
+    raise KeyError(name)

@@ -1,0 +1,275 @@
+"""Pins for the CPU oracle: every oracle function is checked here against
+something other than itself -- an independent method from the paper (integral
+images, the incremental window identities), a library routine (numpy corrcoef,
+argmin, linalg.solve), a closed form, or an exact special case."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2212_00476_amd import scenes
+
+
+def _rand_img(rng, H, W, lo=0, hi=256):
+    return rng.integers(lo, hi, (H, W), dtype=np.int64).astype(np.uint8)
+
+
+def _edge_pad(img, r, left_extra=0):
+    return np.pad(img.astype(np.int64), ((r, r), (r + left_extra, r)), mode="edge")
+
+
+def _box_sum_integral(a, r):
+    """Window sums by the integral image and its four corners (Sec. IV-B,
+    Method 2), on an array already padded by r on every side."""
+    B = np.zeros((a.shape[0] + 1, a.shape[1] + 1), np.int64)
+    B[1:, 1:] = a.cumsum(0).cumsum(1)
+    l = 2 * r + 1
+    return B[l:, l:] - B[:-l, l:] - B[l:, :-l] + B[:-l, :-l]
+
+
+@pytest.mark.parametrize("H,W,D,r", [(7, 9, 4, 1), (11, 13, 6, 2), (5, 17, 9, 3), (6, 6, 1, 0), (4, 5, 7, 4)])
+def test_window_sums_match_integral_image(H, W, D, r):
+    rng = np.random.default_rng(H * 100 + W)
+    L, R = _rand_img(rng, H, W), _rand_img(rng, H, W)
+    S_L, S_LL, S_T, S_TT = oracle.window_sums(L, R, D, r)
+    assert np.array_equal(S_L, _box_sum_integral(_edge_pad(L, r), r))
+    assert np.array_equal(S_LL, _box_sum_integral(_edge_pad(L, r) ** 2, r))
+    # target domain x' = -(D-1) .. W-1: pad D-1 extra replicated columns on the left
+    assert np.array_equal(S_T, _box_sum_integral(_edge_pad(R, r, D - 1), r))
+    assert np.array_equal(S_TT, _box_sum_integral(_edge_pad(R, r, D - 1) ** 2, r))
+
+
+def test_window_sums_hand_example():
+    # 3x3 image, r = 1: the centre window is the whole image; a corner window
+    # replicates the corner row/column (border rule).
+    L = np.array([[1, 2, 3], [4, 5, 6], [7, 8, 9]], np.uint8)
+    S_L, S_LL, S_T, S_TT = oracle.window_sums(L, L, 1, 1)
+    assert S_L[1, 1] == 45 and S_LL[1, 1] == 285
+    # window at (0,0): columns {0,0,1} x rows {0,0,1} -> 4*1 + 2*2 + 2*4 + 5 = 21
+    assert S_L[0, 0] == 21
+
+
+@pytest.mark.parametrize("H,W,D,r", [(8, 10, 5, 1), (9, 12, 7, 2), (6, 7, 10, 3)])
+def test_cross_sums_match_box_filter_of_products(H, W, D, r):
+    rng = np.random.default_rng(7 + r)
+    L, R = _rand_img(rng, H, W), _rand_img(rng, H, W)
+    S = oracle.cross_sums(L, R, D, r)
+    Lp = _edge_pad(L, r)
+    Rp = _edge_pad(R, r, D - 1)          # column index of x' in Rp is x' + D - 1 + r
+    for d in range(D):
+        prod = Lp * Rp[:, D - 1 - d:D - 1 - d + W + 2 * r]
+        assert np.array_equal(S[:, :, d], _box_sum_integral(prod, r)), d
+
+
+def test_cross_sums_incremental_identities():
+    """The two update identities of the zigzag scan (Sec. IV-B): moving the
+    window one row down (or one column right) adds the entering row (column)
+    of products and removes the leaving one.  Checked on the interior where
+    no clamping occurs."""
+    rng = np.random.default_rng(3)
+    H, W, D, r = 12, 16, 4, 2
+    L, R = _rand_img(rng, H, W).astype(np.int64), _rand_img(rng, H, W).astype(np.int64)
+    S = oracle.cross_sums(L.astype(np.uint8), R.astype(np.uint8), D, r)
+    for d in range(D):
+        for y in range(r, H - r - 1):
+            for x in range(r + d, W - r - 1):
+                row_in = sum(L[y + r + 1, x + i] * R[y + r + 1, x - d + i] for i in range(-r, r + 1))
+                row_out = sum(L[y - r, x + i] * R[y - r, x - d + i] for i in range(-r, r + 1))
+                assert S[y + 1, x, d] == S[y, x, d] + row_in - row_out
+                col_in = sum(L[y + j, x + r + 1] * R[y + j, x - d + r + 1] for j in range(-r, r + 1))
+                col_out = sum(L[y + j, x - r] * R[y + j, x - d - r] for j in range(-r, r + 1))
+                assert S[y, x + 1, d] == S[y, x, d] + col_in - col_out
+
+
+def _window(img, x, y, r):
+    H, W = img.shape
+    ys = np.clip(np.arange(y - r, y + r + 1), 0, H - 1)
+    xs = np.clip(np.arange(x - r, x + r + 1), 0, W - 1)
+    return img[np.ix_(ys, xs)].astype(np.float64).ravel()
+
+
+def test_zncc_equals_pearson_correlation():
+    """ZNCC of two windows is their Pearson correlation coefficient."""
+    rng = np.random.default_rng(11)
+    H, W, r = 9, 14, 2
+    L, R = _rand_img(rng, H, W), _rand_img(rng, H, W)
+    for (x, y, d) in [(0, 0, 0), (5, 4, 3), (13, 8, 0), (7, 2, 9), (2, 6, 12), (10, 4, 1)]:
+        a = _window(L, x, y, r)
+        b = _window(R, x - d, y, r)
+        want = np.corrcoef(a, b)[0, 1]
+        assert oracle.zncc_at(L, R, r, x, y, d) == pytest.approx(want, abs=1e-13)
+
+
+def test_zncc_sum_form_agrees_with_definition():
+    """Eq. OP_ZNCC (sums of I, I^2, I_R I_T) against Eq. ZNCC (deviations)."""
+    rng = np.random.default_rng(5)
+    H, W, D, r = 10, 15, 6, 2
+    L, R = _rand_img(rng, H, W), _rand_img(rng, H, W)
+    S_L, S_LL, S_T, S_TT = oracle.window_sums(L, R, D, r)
+    S = oracle.cross_sums(L, R, D, r)
+    cost = oracle.zncc_cost(L, R, D, r)
+    N = (2 * r + 1) ** 2
+    for y in range(H):
+        for x in range(W):
+            for d in range(D):
+                st, stt = S_T[y, x - d + D - 1], S_TT[y, x - d + D - 1]
+                vl, vt = N * S_LL[y, x] - S_L[y, x] ** 2, N * stt - st ** 2
+                z2 = 0.0 if vl == 0 or vt == 0 else (N * S[y, x, d] - S_L[y, x] * st) / math.sqrt(float(vl * vt))
+                assert 1.0 - cost[y, x, d] == pytest.approx(z2, abs=1e-12)
+
+
+def test_zncc_special_cases():
+    rng = np.random.default_rng(1)
+    H, W, r = 8, 12, 1
+    base = rng.integers(20, 100, (H, W)).astype(np.uint8)
+    # identical images: ZNCC(d=0) = 1 wherever the window has variance
+    assert oracle.zncc_at(base, base, r, 5, 4, 0) == 1.0
+    # exact integer gain and bias without clipping: still 1
+    affine = (2 * base.astype(np.int64) + 7).astype(np.uint8)
+    assert oracle.zncc_at(base, affine, r, 5, 4, 0) == pytest.approx(1.0, abs=1e-15)
+    # inverted target: -1
+    inv = (255 - base.astype(np.int64)).astype(np.uint8)
+    assert oracle.zncc_at(base, inv, r, 6, 3, 0) == pytest.approx(-1.0, abs=1e-15)
+    # a shifted copy is found at its shift
+    shifted = np.roll(base, -3, axis=1)       # right(x') = left(x'+3) -> d = 3
+    c = [oracle.zncc_at(base, shifted, r, 8, 4, d) for d in range(6)]
+    assert int(np.argmax(c)) == 3 and c[3] == pytest.approx(1.0, abs=1e-15)
+    # zero-variance window on either side: ZNCC 0, cost 1
+    flat = np.full((H, W), 77, np.uint8)
+    assert oracle.zncc_at(flat, base, r, 5, 4, 0) == 0.0
+    assert oracle.zncc_at(base, flat, r, 5, 4, 2) == 0.0
+    assert oracle.zncc_cost_slice(flat, flat, r, 0)[3, 3] == 1.0
+
+
+def test_zncc_range_and_target_gain_bias_invariance():
+    p = scenes.bands_pair(W=64, H=24, D=16, seed=4, band_disps=(3, 9))
+    cost = oracle.zncc_cost(p.left, p.right, 16, 2)
+    assert cost.min() >= 0.0 and cost.max() <= 2.0
+    # integer gain/bias applied to the target, away from clipping: costs unchanged
+    R = np.clip(p.right.astype(np.int64), 40, 120)
+    R2 = (2 * R + 9).astype(np.uint8)
+    c1 = oracle.zncc_cost(p.left, R.astype(np.uint8), 16, 2)
+    c2 = oracle.zncc_cost(p.left, R2, 16, 2)
+    assert np.abs(c1 - c2).max() < 1e-12
+
+
+def test_dt_weights_power_form():
+    """Eq. k1-k4 in the power form a^(1 + (sigma_s/sigma_r)|dI|), a = exp(-1/sigma_s),
+    against the simplified exponential the oracle uses (Eq. weight)."""
+    rng = np.random.default_rng(2)
+    G = _rand_img(rng, 6, 9)
+    ss, sr = 20.0, 0.1
+    wh, wv = oracle.dt_weights(G, ss, sr)
+    a = math.exp(-1.0 / ss)
+    g = G.astype(np.int64)
+    for y in range(6):
+        for x in range(9):
+            if x >= 1:
+                assert wh[y, x] == pytest.approx(a ** (1 + (ss / (255 * sr)) * abs(g[y, x] - g[y, x - 1])), rel=1e-12)
+            else:
+                assert wh[y, x] == 0.0
+            if y >= 1:
+                assert wv[y, x] == pytest.approx(a ** (1 + (ss / (255 * sr)) * abs(g[y, x] - g[y - 1, x])), rel=1e-12)
+            else:
+                assert wv[y, x] == 0.0
+    # flat guide or disabled range term: every interior weight is K = exp(-1/sigma_s)
+    wh, wv = oracle.dt_weights(G, ss, math.inf)
+    assert np.allclose(wh[:, 1:], a, rtol=1e-15) and np.allclose(wv[1:, :], a, rtol=1e-15)
+
+
+def _pair_matrix(n, K):
+    """Closed form of one causal + anticausal pass with constant weight K
+    (boundaries as in Eqs. DT1-DT2):
+    h(x, u) = K^|x-u| (1 - K^(2(n - max(x,u)))) / (1 - K^2)."""
+    x = np.arange(n)[:, None]
+    u = np.arange(n)[None, :]
+    m = np.maximum(x, u)
+    return K ** np.abs(x - u) * (1.0 - K ** (2 * (n - m))) / (1.0 - K * K)
+
+
+@pytest.mark.parametrize("iters", [1, 3])
+def test_dt_constant_weight_closed_form(iters):
+    rng = np.random.default_rng(9)
+    H, W, ss = 7, 11, 5.0
+    K = math.exp(-1.0 / ss)
+    G = np.full((H, W), 100, np.uint8)           # flat guide: all weights K
+    wh, wv = oracle.dt_weights(G, ss, 0.1)
+    c = rng.uniform(0, 2, (H, W))
+    got = oracle.dt_slice(c, wh, wv, iters)
+    Ah, Av = _pair_matrix(W, K), _pair_matrix(H, K)
+    want = c.copy()
+    for _ in range(iters):
+        want = Av @ (want @ Ah.T)
+    assert np.allclose(got, want, rtol=1e-12, atol=0)
+    # in the interior of a long line the pair filter is the symmetric K^|n| / (1 - K^2)
+    A = _pair_matrix(401, K)
+    assert A[200, 203] == pytest.approx(K ** 3 / (1 - K * K), rel=1e-12)
+
+
+def test_dt_equals_dense_linear_solves():
+    """Each DT pass is a bidiagonal linear system; solve it with numpy."""
+    rng = np.random.default_rng(12)
+    H, W = 6, 8
+    G = _rand_img(rng, H, W)
+    wh, wv = oracle.dt_weights(G, 20.0, 0.1)
+    c = rng.uniform(0, 2, (H, W))
+    got = oracle.dt_slice(c, wh, wv, 2)
+
+    def causal(wgt):           # (I - diag(w) S) y = b,  y[i] = b[i] + w[i] y[i-1]
+        n = len(wgt)
+        return np.eye(n) - np.diag(wgt[1:], -1)
+
+    def anticausal(wgt):       # y[i] = b[i] + w[i+1] y[i+1]
+        n = len(wgt)
+        return np.eye(n) - np.diag(wgt[1:], 1)
+
+    v = c.copy()
+    for _ in range(2):
+        for y in range(H):
+            v[y] = np.linalg.solve(causal(wh[y]), v[y])
+            v[y] = np.linalg.solve(anticausal(wh[y]), v[y])
+        for x in range(W):
+            v[:, x] = np.linalg.solve(causal(wv[:, x]), v[:, x])
+            v[:, x] = np.linalg.solve(anticausal(wv[:, x]), v[:, x])
+    assert np.allclose(got, v, rtol=1e-12, atol=1e-13)
+
+
+def test_dt_volume_is_slicewise_and_linear():
+    rng = np.random.default_rng(4)
+    H, W, D = 5, 7, 3
+    G = _rand_img(rng, H, W)
+    wh, wv = oracle.dt_weights(G, 10.0, 0.2)
+    a, b = rng.uniform(0, 2, (H, W, D)), rng.uniform(0, 2, (H, W, D))
+    va = oracle.dt_aggregate(a, wh, wv, 2)
+    for d in range(D):
+        assert np.array_equal(va[:, :, d], oracle.dt_slice(a[:, :, d], wh, wv, 2))
+    vab = oracle.dt_aggregate(2.0 * a - 0.5 * b, wh, wv, 2)
+    vb = oracle.dt_aggregate(b, wh, wv, 2)
+    assert np.allclose(vab, 2.0 * va - 0.5 * vb, rtol=1e-12, atol=1e-12)
+    # a d-independent offset moves every slice by the same field: argmin unchanged
+    off = rng.uniform(0, 5, (H, W, 1))
+    assert np.array_equal(oracle.wta(oracle.dt_aggregate(a + off, wh, wv, 2)), oracle.wta(va))
+
+
+def test_wta_matches_numpy_argmin_with_ties():
+    rng = np.random.default_rng(8)
+    v = rng.integers(0, 4, (6, 7, 9)).astype(np.float64)     # many exact ties
+    assert np.array_equal(oracle.wta(v), np.argmin(v, axis=2).astype(np.int32))
+
+
+def test_band_scene_exact_recovery():
+    """Three vertical bands at d = 5, 12, 20 (320x96, D = 32, 9x9): plain WTA
+    recovers every pixel whose window stays clear of band edges and borders;
+    with DT the central half of each band is recovered."""
+    p = scenes.bands_pair()
+    D, r = 32, 4
+    disp0 = oracle.wta(oracle.zncc_cost(p.left, p.right, D, r))
+    disp3 = oracle.stereo_solve(p.left, p.right, D, r, 20.0, 0.1, 3)
+    maxd = max(p.band_disps)
+    for k, d in enumerate(p.band_disps):
+        lo, hi = p.band_edges[k], p.band_edges[k + 1]
+        xs = slice(max(lo + maxd + r, d + r), hi - maxd - r)
+        assert np.all(disp0[r:-r, xs] == d), k
+        q = (hi - lo) // 4
+        assert np.all(disp3[:, max(lo + q, d + r):hi - q] == d), k

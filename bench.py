@@ -1,0 +1,183 @@
+"""Benchmark of the stereo hot path on one MI355X.
+
+One step = one stereo_solve of a 1280x384 pair, D = 128, 9x9 ZNCC window, DT
+with sigma_s = 20, sigma_r = 0.1 and 3 sweeps, WTA -- the cost, all twelve DT
+passes and the WTA, on inputs already resident in HBM.  The headline value is
+FP32-volume throughput in G cost evaluations per second (W*H*D per step); the
+same line carries the FP16 and BF16 forms, the unfused FP32 per-pair form, the
+roofline of the dominant kernel and the CPU oracle timed on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+W, H, D, R = 1280, 384, 128, 4
+SIGMA_S, SIGMA_R, ITERS = 20.0, 0.1, 3
+WORKLOAD = "planes_1280x384_d128"
+PEAK_HBM_GBS = 8000.0
+METRIC = "Gcost-evals/s & fps at 1280x384 D=128 (FP32 vs FP16 vol); p99 latency served"
+KERNEL_SOURCES = ("paper_2212_00476_amd/csrc/zdt_device.hpp",)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(kernel, s):
+    """Compulsory HBM bytes of one launch at this workload (s = bytes per volume element)."""
+    nvol, npix = W * H * D, W * H
+    return {
+        "zncc_hpair": nvol * s + 2 * npix,             # write the volume; read both images
+        "zncc_cost": nvol * s + 2 * npix,
+        "dt_hpair": 2 * nvol * s + npix,               # read + write the volume; read the guide
+        "dt_vpair": 2 * nvol * s + npix,
+        "dt_vpair_wta": nvol * s + npix + 4 * npix,    # read the volume and guide; write disparities
+        "wta": nvol * s + 4 * npix,
+    }.get(kernel)
+
+
+def measured_traffic(kernel, vol_dtype):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, vol_dtype))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def time_steps(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(steps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / steps
+
+
+def cpu_baseline(left, right, n_slices, threads):
+    import oracle
+    ds = list(range(0, D, max(1, D // n_slices)))[:n_slices]
+    t0 = time.perf_counter()
+    oracle.solve_slices(left, right, R, ds, SIGMA_S, SIGMA_R, ITERS, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": round(W * H * len(ds) / dt / 1e9, 6), "unit": "Gcost-evals/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d of %d disparity slices of the 1280x384 pair (cost + 3-sweep DT per slice, FP64), "
+                      "%.1f s wall on %d threads" % (len(ds), D, dt, threads)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-slices", type=int, default=64)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs the whole pair on a single MI355X "
+              "(sharding by disparity range is described, not built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2212_00476_amd as zdt
+    from paper_2212_00476_amd import scenes
+
+    zdt.load()
+    pr = scenes.workload(WORKLOAD)
+    dev = torch.device("cuda:0")
+    L = torch.from_numpy(pr.left).to(dev)
+    Rt = torch.from_numpy(pr.right).to(dev)
+    nvol = W * H * D
+
+    forms = {}
+    solvers = {}
+    for name, dt in (("f32", zdt.ZDT_F32), ("f16", zdt.ZDT_F16), ("bf16", zdt.ZDT_BF16)):
+        p = zdt.params(W, H, D, R, SIGMA_S, SIGMA_R, ITERS, vol_dtype=dt)
+        solver = zdt.Solver(p, device=dev)
+        disp = torch.empty((H, W), dtype=torch.int32, device=dev)
+        solvers[name] = (solver, disp)
+        ms = time_steps(lambda: solver(L, Rt, disp), args.steps, args.warmup, torch)
+        forms[name] = {"ms_per_step": round(ms, 5), "gcost_evals_per_s": round(nvol / (ms * 1e-3) / 1e9, 3),
+                       "fps": round(1000.0 / ms, 1)}
+
+    # the plain FP32 per-pair form: raw cost volume, 12 unfused DT passes, WTA
+    p32 = zdt.params(W, H, D, R, SIGMA_S, SIGMA_R, ITERS)
+    vol = torch.empty((H, W, D), dtype=torch.float32, device=dev)
+    disp_u = torch.empty((H, W), dtype=torch.int32, device=dev)
+
+    def unfused():
+        zdt.zncc_cost_volume(p32, L, Rt, vol)
+        zdt.dt_aggregate(p32, L, vol)
+        zdt.wta_disparity(p32, vol, disp_u)
+    ms_u = time_steps(unfused, max(10, args.steps // 4), 5, torch)
+    forms["unfused_f32"] = {"ms_per_step": round(ms_u, 5), "gcost_evals_per_s": round(nvol / (ms_u * 1e-3) / 1e9, 3),
+                            "fps": round(1000.0 / ms_u, 1)}
+
+    # per-kernel HIP-event times over the timed steps of the FP32 form
+    solver, disp = solvers["f32"]
+    for _ in range(args.warmup):
+        solver(L, Rt, disp)
+    torch.cuda.synchronize()
+    zdt.profile_enable(True)
+    for _ in range(args.steps):
+        solver(L, Rt, disp)
+    torch.cuda.synchronize()
+    kt = zdt.profile_collect()
+    zdt.profile_enable(False)
+    kernels = {k: {"avg_us": round(1e3 * ms / n, 3), "launches": n} for k, (ms, n) in kt.items()}
+    dom = max(kt, key=lambda k: kt[k][0])
+    avg_s = kt[dom][0] / kt[dom][1] * 1e-3
+    abytes = algorithmic_bytes(dom, 4)
+    achieved = abytes / avg_s / 1e9
+    traffic = measured_traffic(dom, "f32")
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                "algorithmic_bytes": abytes, "avg_us": round(avg_s * 1e6, 3)}
+    for k in kernels:
+        b = algorithmic_bytes(k, 4)
+        if b:
+            kernels[k]["GBps"] = round(b / (kernels[k]["avg_us"] * 1e-6) / 1e9, 1)
+
+    cpu = None
+    if not args.no_cpu:
+        threads = min(16, os.cpu_count() or 1)
+        cpu = cpu_baseline(pr.left, pr.right, args.cpu_slices, threads)
+
+    f32 = forms["f32"]
+    line = {
+        "metric": METRIC, "value": f32["gcost_evals_per_s"], "unit": "Gcost-evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": f32["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": WORKLOAD, "width": W, "height": H, "max_disp": D, "window": 2 * R + 1,
+                   "sigma_s": SIGMA_S, "sigma_r": SIGMA_R, "dt_iters": ITERS, "vol_dtype": "f32",
+                   "parallelism": "single-gpu"},
+        "fps": f32["fps"], "forms": forms, "kernels_f32": kernels, "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,137 @@
+/*
+ * zdt.h -- C ABI of the MI355X (gfx950) stereo hot path:
+ *   ZNCC matching cost  ->  domain-transform (DT) aggregation  ->  WTA.
+ *
+ * Method: "Efficient Stereo Matching on Embedded GPUs with Zero-Means Cross
+ * Correlation" (Chang et al., arXiv 2212.00476).  Each entry point cites the
+ * passage that defines the operation it runs.
+ *
+ * Conventions shared by every entry point
+ *   - Images are 8-bit grayscale, row-major, `pitch` bytes between rows.
+ *     left = reference I_R, right = target I_T; a candidate pairs I_R(x,y)
+ *     with I_T(x-d,y), d in [0, D) (Sec. III-A).
+ *   - Every pixel read is clamped to the image (replicate border); target
+ *     columns x-d+i < 0 read column 0.
+ *   - A cost volume is [H][W][D] with d fastest (element (x,y,d) at
+ *     ((y*W + x)*D + d)), stored as float32, float16 or bfloat16
+ *     (`vol_dtype`).  The cost is 1 - ZNCC in [0, 2].
+ *   - Pointers to images, volumes, disparities and workspace are DEVICE
+ *     pointers owned by the caller; the library never frees or keeps them.
+ *     `params` and the `applied_scale` output are HOST pointers.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *     their kernels and return without synchronising.  Argument errors are
+ *     reported synchronously with nothing enqueued; a failed launch returns
+ *     ZDT_EHIP.  zdt_last_error() gives a message for the calling thread's
+ *     last failure.
+ *   - Calls that share a volume or workspace must be ordered by the caller
+ *     (same stream, or events); calls on disjoint buffers may overlap.
+ */
+#ifndef ZDT_H
+#define ZDT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum zdt_status {
+  ZDT_OK = 0,
+  ZDT_EINVAL = -1,          /* a parameter or pointer is invalid            */
+  ZDT_ENOMEM = -2,          /* a host-side allocation failed                */
+  ZDT_EHIP = -3,            /* a HIP call or kernel launch failed           */
+  ZDT_EUNSUPPORTED = -4     /* valid, but outside what this build supports  */
+} zdt_status;
+
+typedef enum zdt_dtype { ZDT_F32 = 0, ZDT_F16 = 1, ZDT_BF16 = 2 } zdt_dtype;
+
+/* flags */
+#define ZDT_FLAG_NORMALIZE 1     /* scale each DT pass by (1 - K); forced for F16/BF16 */
+#define ZDT_FLAG_GUIDE_TARGET 2  /* DT weights from the target (right) image instead of the reference */
+
+typedef struct zdt_params {
+  int32_t width;        /* W >= 1                                                      */
+  int32_t height;       /* H >= 1                                                      */
+  int32_t pitch;        /* bytes between image rows, >= W                              */
+  int32_t max_disp;     /* D >= 1; candidates d = 0 .. D-1                             */
+  int32_t radius;       /* r, window side l = 2r+1; 0 <= r <= 6 (int32-exact sums)     */
+  float sigma_s;        /* DT spatial parameter, > 0 (Eq. a: a = K = exp(-1/sigma_s))  */
+  float sigma_r;        /* DT range parameter in intensity/255 units, > 0; +inf turns  */
+                        /* the range term off                                          */
+  int32_t dt_iters;     /* I >= 0 sweeps of the four DT passes (0 = no aggregation)    */
+  int32_t vol_dtype;    /* zdt_dtype of every cost volume the call reads or writes     */
+  int32_t flags;        /* ZDT_FLAG_*                                                  */
+  int32_t reserved[4];  /* must be zero                                                */
+} zdt_params;
+
+/* Bytes of device workspace that stereo_solve() needs besides its volume
+ * (0 means `ws` may be NULL).  Returns 0 for invalid parameters as well; the
+ * entry points report those. */
+size_t zdt_workspace_size(const zdt_params* params);
+
+/* Bytes of one cost volume for these parameters: W*H*D*sizeof(vol_dtype). */
+size_t zdt_volume_size(const zdt_params* params);
+
+/* Matching-cost volume (Sec. III-A, Eq. ZNCC, evaluated through the sum form
+ * of Eq. OP_ZNCC from exact int32 window sums):
+ *   cost(x,y,d) = 1 - clamp(ZNCC(x,y,d), -1, 1), written to `cost_hwd`.
+ * A window of zero variance (on either side) gives ZNCC = 0, i.e. cost 1. */
+int zncc_cost_volume(const zdt_params* params, const uint8_t* left, const uint8_t* right, void* cost_hwd,
+                     void* stream);
+
+/* DT aggregation in place on `cost_hwd` (Sec. III-B, Eqs. DT1-DT4 with the
+ * edge weights of Eqs. k1-k4 / weight computed from `guide`):
+ *   per sweep, for every d:  L along +x, R along -x, U along +y, D along -y,
+ *   with W_L(x) = exp(-1/sigma_s - |G(x)-G(x-1)|/(255 sigma_r)), W_R(x) = W_L(x+1),
+ *   and the same vertically; repeated dt_iters times.
+ * `guide` is the reference image (the weights' image; the caller passes the
+ * target to follow ZDT_FLAG_GUIDE_TARGET).  The recursion state is float32.
+ * With ZDT_FLAG_NORMALIZE (always on for F16/BF16) every pass is scaled by
+ * (1 - K); the volume returned is then s_total * C_agg with
+ * s_total = (1-K)^(4*dt_iters), written to *applied_scale when it is not NULL
+ * (1.0 without normalisation).  Scaling leaves the argmin unchanged. */
+int dt_aggregate(const zdt_params* params, const uint8_t* guide, void* cost_hwd, double* applied_scale,
+                 void* stream);
+
+/* Winner-take-all (Sec. III-C, Eq. WTA1): disp(x,y) = the smallest d with
+ * cost(x,y,d) = min_d' cost(x,y,d').  `disp_hw` is int32 [H][W]. */
+int wta_disparity(const zdt_params* params, const void* cost_hwd, int32_t* disp_hw, void* stream);
+
+/* The whole path for one pair: cost (Sec. III-A), DT (Sec. III-B), WTA
+ * (Sec. III-C), with the cost fused into the first horizontal pass pair and the
+ * WTA fused into the last vertical pass pair (the fusion boundaries of
+ * Sec. V-C).  `vol_hwd` is a caller-owned volume of zdt_volume_size() bytes
+ * used as the working volume; its contents on return are unspecified.  `ws`
+ * holds zdt_workspace_size() bytes (may be NULL when that is 0).  With
+ * dt_iters = 0 this is the WTA of the raw cost. */
+int stereo_solve(const zdt_params* params, const uint8_t* left, const uint8_t* right, int32_t* disp_hw,
+                 void* vol_hwd, void* ws, void* stream);
+
+/* Exact integer sums behind the cost (Sec. IV-B summation and the Pi_RT term
+ * of Eq. OP_ZNCC), exposed for verification; any output pointer may be NULL:
+ *   s_l, s_ll      [H][W]        sum of I_R and I_R^2 over the window at (x,y)
+ *   s_t, s_tt      [H][W+D-1]    sum of I_T and I_T^2 over the window at x',
+ *                                x' = -(D-1) .. W-1 stored at index x'+D-1
+ *   s_rt           [H][W][D]     sum over the window of I_R(x+i,y+j) I_T(x-d+i,y+j)
+ * All int32 (exact: l <= 13 keeps every sum below 2^31). */
+int zncc_window_sums(const zdt_params* params, const uint8_t* left, const uint8_t* right, int32_t* s_l,
+                     int32_t* s_ll, int32_t* s_t, int32_t* s_tt, int32_t* s_rt, void* stream);
+
+/* Message for the calling thread's last non-OK return ("" if none). */
+const char* zdt_last_error(void);
+
+/* Kernel timing.  zdt_profile_enable(1) clears the records and makes every
+ * later launch on any stream record a HIP event pair around itself on that
+ * stream; zdt_profile_enable(0) stops recording.  zdt_profile_collect()
+ * synchronises on the recorded events and returns the number of distinct
+ * kernel names seen; zdt_profile_entry() reads one of them: its name (static
+ * storage), the summed milliseconds and the number of launches. */
+int zdt_profile_enable(int on);
+int zdt_profile_collect(void);
+int zdt_profile_entry(int index, const char** name, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ZDT_H */

@@ -46,6 +46,8 @@ def _load():
         Dbl = ctypes.c_double
         lib.oracle_window_sums.argtypes = [P, P, I, I, I, I, I, P, P, P, P]
         lib.oracle_cross_sums.argtypes = [P, P, I, I, I, I, I, P]
+        lib.oracle_cross_sum_at.argtypes = [P, P, I, I, I, I, I, I, I]
+        lib.oracle_cross_sum_at.restype = ctypes.c_int64
         lib.oracle_zncc_at.argtypes = [P, P, I, I, I, I, I, I, I]
         lib.oracle_zncc_at.restype = Dbl
         lib.oracle_zncc_cost_slice.argtypes = [P, P, I, I, I, I, I, P]
@@ -98,6 +100,13 @@ def cross_sums(left, right, D, r):
     out = np.empty((H, W, D), np.int64)
     _check(_load().oracle_cross_sums(_ptr(L), _ptr(R), W, W, H, D, r, _ptr(out)), "cross_sums")
     return out
+
+
+def cross_sum_at(left, right, r, x, y, d):
+    """int S_RT(x, y, d) for one element."""
+    L, R = _u8(left), _u8(right)
+    H, W = L.shape
+    return int(_load().oracle_cross_sum_at(_ptr(L), _ptr(R), W, W, H, r, x, y, d))
 
 
 def zncc_at(left, right, r, x, y, d):

@@ -97,6 +97,15 @@ int oracle_cross_sums(const uint8_t* L, const uint8_t* R, int pitch, int W, int 
   return 0;
 }
 
+/* One element of the cross sum above. */
+int64_t oracle_cross_sum_at(const uint8_t* L, const uint8_t* R, int pitch, int W, int H, int r, int x, int y, int d) {
+  int64_t s = 0;
+  for (int j = -r; j <= r; ++j)
+    for (int i = -r; i <= r; ++i)
+      s += (int64_t)pix(L, pitch, W, H, x + i, y + j) * pix(R, pitch, W, H, x - d + i, y + j);
+  return s;
+}
+
 /* ---------------------------------------------------------------------------
  * ZNCC by its defining formula (Eq. ZNCC): deviations from the window means,
  * their cross sum over the standard deviations.  Returns z in [-1, 1].

@@ -1,0 +1,45 @@
+"""MI355X-native ZNCC + domain-transform + WTA stereo matching.
+
+The compute path is the HIP library ``libzdt.so`` (C ABI: ``include/zdt.h``);
+this package is its thin Python binding plus the seeded scene generator used by
+the tests and the benchmark.  PyTorch provides device memory and streams only.
+
+    import torch, paper_2212_00476_amd as zdt
+    p = zdt.params(1280, 384, 128, radius=4, sigma_s=20, sigma_r=0.1, dt_iters=3)
+    solver = zdt.Solver(p)
+    disp = solver(left_u8_cuda, right_u8_cuda)      # int32 [H][W] on the device
+"""
+from __future__ import annotations
+
+from ._lib import (ZDT_BF16, ZDT_F16, ZDT_F32, ZDT_FLAG_GUIDE_TARGET, ZDT_FLAG_NORMALIZE, ZdtError, ZdtParams,
+                   dt_aggregate, load, params, profile_collect, profile_enable, stereo_solve, volume_size,
+                   workspace_size, wta_disparity, zncc_cost_volume, zncc_window_sums)
+
+__all__ = ["ZDT_F32", "ZDT_F16", "ZDT_BF16", "ZDT_FLAG_NORMALIZE", "ZDT_FLAG_GUIDE_TARGET", "ZdtError", "ZdtParams",
+           "params", "load", "zncc_cost_volume", "dt_aggregate", "wta_disparity", "stereo_solve", "zncc_window_sums",
+           "workspace_size", "volume_size", "profile_enable", "profile_collect", "torch_dtype", "Solver"]
+
+
+def torch_dtype(vol_dtype):
+    import torch
+    return {ZDT_F32: torch.float32, ZDT_F16: torch.float16, ZDT_BF16: torch.bfloat16}[vol_dtype]
+
+
+class Solver:
+    """One pair shape: owns the working volume and workspace on the device."""
+
+    def __init__(self, p, device="cuda"):
+        import torch
+        load()
+        self.p = p
+        self.device = torch.device(device)
+        self.vol = torch.empty((p.height, p.width, p.max_disp), dtype=torch_dtype(p.vol_dtype), device=self.device)
+        ws = workspace_size(p)
+        self.ws = torch.empty(ws, dtype=torch.uint8, device=self.device) if ws else None
+
+    def __call__(self, left, right, disp=None, stream=None):
+        import torch
+        if disp is None:
+            disp = torch.empty((self.p.height, self.p.width), dtype=torch.int32, device=self.device)
+        stereo_solve(self.p, left, right, disp, self.vol, self.ws, stream)
+        return disp

@@ -1,0 +1,144 @@
+"""ctypes binding of ``libzdt.so`` (the C ABI in ``include/zdt.h``).
+
+Argument marshalling only: tensors are passed as raw device pointers and every
+step runs in the library's HIP kernels.  There is no CPU fallback; if the
+library is not built, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libzdt.so")
+
+ZDT_OK, ZDT_EINVAL, ZDT_ENOMEM, ZDT_EHIP, ZDT_EUNSUPPORTED = 0, -1, -2, -3, -4
+ZDT_F32, ZDT_F16, ZDT_BF16 = 0, 1, 2
+ZDT_FLAG_NORMALIZE = 1
+ZDT_FLAG_GUIDE_TARGET = 2
+
+EXPORTED = ("zdt_workspace_size", "zdt_volume_size", "zncc_cost_volume", "dt_aggregate", "wta_disparity",
+            "stereo_solve", "zncc_window_sums", "zdt_last_error", "zdt_profile_enable", "zdt_profile_collect",
+            "zdt_profile_entry")
+
+
+class ZdtParams(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("pitch", ctypes.c_int32),
+                ("max_disp", ctypes.c_int32), ("radius", ctypes.c_int32), ("sigma_s", ctypes.c_float),
+                ("sigma_r", ctypes.c_float), ("dt_iters", ctypes.c_int32), ("vol_dtype", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+
+
+class ZdtError(RuntimeError):
+    def __init__(self, fn, code, msg):
+        super().__init__(f"{fn} failed ({code}): {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libzdt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library {LIB_PATH} is not built; run `python -m paper_2212_00476_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, PP = ctypes.c_void_p, ctypes.POINTER(ZdtParams)
+    lib.zdt_workspace_size.argtypes = [PP]
+    lib.zdt_workspace_size.restype = ctypes.c_size_t
+    lib.zdt_volume_size.argtypes = [PP]
+    lib.zdt_volume_size.restype = ctypes.c_size_t
+    lib.zncc_cost_volume.argtypes = [PP, P, P, P, P]
+    lib.dt_aggregate.argtypes = [PP, P, P, ctypes.POINTER(ctypes.c_double), P]
+    lib.wta_disparity.argtypes = [PP, P, P, P]
+    lib.stereo_solve.argtypes = [PP, P, P, P, P, P, P]
+    lib.zncc_window_sums.argtypes = [PP, P, P, P, P, P, P, P, P]
+    lib.zdt_last_error.restype = ctypes.c_char_p
+    lib.zdt_profile_enable.argtypes = [ctypes.c_int]
+    lib.zdt_profile_entry.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    for f in ("zncc_cost_volume", "dt_aggregate", "wta_disparity", "stereo_solve", "zncc_window_sums",
+              "zdt_profile_enable", "zdt_profile_collect", "zdt_profile_entry"):
+        getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def params(width, height, max_disp, radius=4, sigma_s=20.0, sigma_r=0.1, dt_iters=3, vol_dtype=ZDT_F32, flags=0,
+           pitch=None):
+    return ZdtParams(int(width), int(height), int(pitch if pitch is not None else width), int(max_disp), int(radius),
+                     float(sigma_s), float(sigma_r), int(dt_iters), int(vol_dtype), int(flags),
+                     (ctypes.c_int32 * 4)(0, 0, 0, 0))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _check(fn, rc):
+    if rc != ZDT_OK:
+        raise ZdtError(fn, rc, load().zdt_last_error().decode())
+
+
+def workspace_size(p):
+    return int(load().zdt_workspace_size(ctypes.byref(p)))
+
+
+def volume_size(p):
+    return int(load().zdt_volume_size(ctypes.byref(p)))
+
+
+def zncc_cost_volume(p, left, right, cost, stream=None):
+    _check("zncc_cost_volume",
+           load().zncc_cost_volume(ctypes.byref(p), _ptr(left), _ptr(right), _ptr(cost), _stream(stream)))
+
+
+def dt_aggregate(p, guide, cost, stream=None):
+    scale = ctypes.c_double(math.nan)
+    _check("dt_aggregate",
+           load().dt_aggregate(ctypes.byref(p), _ptr(guide), _ptr(cost), ctypes.byref(scale), _stream(stream)))
+    return scale.value
+
+
+def wta_disparity(p, cost, disp, stream=None):
+    _check("wta_disparity", load().wta_disparity(ctypes.byref(p), _ptr(cost), _ptr(disp), _stream(stream)))
+
+
+def stereo_solve(p, left, right, disp, vol, ws=None, stream=None):
+    _check("stereo_solve", load().stereo_solve(ctypes.byref(p), _ptr(left), _ptr(right), _ptr(disp), _ptr(vol),
+                                               _ptr(ws), _stream(stream)))
+
+
+def zncc_window_sums(p, left, right, s_l=None, s_ll=None, s_t=None, s_tt=None, s_rt=None, stream=None):
+    _check("zncc_window_sums",
+           load().zncc_window_sums(ctypes.byref(p), _ptr(left), _ptr(right), _ptr(s_l), _ptr(s_ll), _ptr(s_t),
+                                   _ptr(s_tt), _ptr(s_rt), _stream(stream)))
+
+
+def profile_enable(on):
+    _check("zdt_profile_enable", load().zdt_profile_enable(int(bool(on))))
+
+
+def profile_collect():
+    """{kernel name: (total ms, launches)} for the launches recorded since profile_enable(True)."""
+    lib = load()
+    n = lib.zdt_profile_collect()
+    if n < 0:
+        _check("zdt_profile_collect", n)
+    out = {}
+    for i in range(n):
+        name, ms, cnt = ctypes.c_char_p(), ctypes.c_double(), ctypes.c_int64()
+        _check("zdt_profile_entry", lib.zdt_profile_entry(i, ctypes.byref(name), ctypes.byref(ms), ctypes.byref(cnt)))
+        out[name.value.decode()] = (ms.value, cnt.value)
+    return out

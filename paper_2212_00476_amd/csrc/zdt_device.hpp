@@ -1,0 +1,676 @@
+// zdt_device.hpp -- gfx950 kernels of the stereo hot path.
+//
+//   hpass_kernel   one workgroup per (row y, chunk of 64 disparities); lanes map
+//                  to d, each wave owns one contiguous x-segment of the row.
+//                  Modes: the exact int32 cross sums, the ZNCC cost (Sec. III-A,
+//                  Eq. OP_ZNCC), the cost fused with the L and R passes
+//                  (Eqs. DT1-DT2), or the L and R passes over a stored volume.
+//   vpass_kernel   one workgroup per (column x, chunk of 64*DPL disparities);
+//                  lanes map to d, each wave owns one y-segment of the column.
+//                  U and D passes (Eqs. DT3-DT4), optionally fused with the WTA
+//                  of Eq. WTA1 so that the last volume is never written.
+//   wta_kernel     standalone WTA over a stored volume; one wave per pixel.
+//
+// A line (a row for H, a column for V) is split into one segment per wave.
+// Every pass is a first-order linear recursion c[i] += w[i] * c[i-1], so a
+// segment's result is its carry-free local result plus (product of its
+// weights) x (carry in).  The carries are composed across the segments of the
+// workgroup through LDS, then each segment re-runs its recursion from the true
+// carry: the values written are the sequential recursion of the paper, apart
+// from the rounding of the carries.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace zdt {
+
+constexpr int kWave = 64;
+constexpr int kMaxWaves = 16;
+
+struct bf16 {
+  uint16_t bits;
+};
+
+template <typename T>
+struct Elem;
+template <>
+struct Elem<float> {
+  static __device__ __forceinline__ float load(const float* p) { return *p; }
+  static __device__ __forceinline__ void store(float* p, float v) { *p = v; }
+};
+template <>
+struct Elem<_Float16> {
+  static __device__ __forceinline__ float load(const _Float16* p) { return (float)*p; }
+  static __device__ __forceinline__ void store(_Float16* p, float v) { *p = (_Float16)v; }
+};
+template <>
+struct Elem<bf16> {
+  static __device__ __forceinline__ float load(const bf16* p) { return __uint_as_float((uint32_t)p->bits << 16); }
+  static __device__ __forceinline__ void store(bf16* p, float v) {
+    uint32_t u = __float_as_uint(v);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even (values are finite)
+    p->bits = (uint16_t)(u >> 16);
+  }
+};
+
+__host__ __device__ constexpr int packs_of(int R) { return (2 * R + 1 + 3) / 4; }
+
+// ---------------------------------------------------------------------------
+// LDS layout of hpass_kernel, in 32-bit words.
+//   LP[k][W+2R]  packed column bytes of the reference rows y-R..y+R: entry i is
+//                column clamp(i-R); byte j of pack k is row y-R+4k+j (clamped),
+//                zero past row y+R.
+//   LS, LI [W]   S_R(x) and 1/sqrt(l^2 S_RR - S_R^2) (0 for zero variance).
+//   TP[k][W+63+2R] packed target columns; entry i is column clamp(i-63-R-d0).
+//   TS, TI [W+63] target window sum and inverse deviation at x' = t-63-d0.
+//   WH[W+1]      W_L(x) for x in [0, W]; WH[0] = WH[W] = 0.
+//   EX, EX2 [16][64], EXS, EXS2 [16]   segment carries.
+// ---------------------------------------------------------------------------
+struct HLayout {
+  int nLP, nTP, oLP, oLS, oLI, oTP, oTS, oTI, oWH, oEX, oEXS, oEX2, oEXS2, words;
+};
+
+__host__ __device__ inline HLayout h_layout(int W, int R, bool zncc, bool dt) {
+  HLayout L{};
+  const int NP = packs_of(R);
+  L.nLP = W + 2 * R;
+  L.nTP = W + 63 + 2 * R;
+  int o = 0;
+  if (zncc) {
+    L.oLP = o; o += NP * L.nLP;
+    L.oLS = o; o += W;
+    L.oLI = o; o += W;
+    L.oTP = o; o += NP * L.nTP;
+    L.oTS = o; o += W + 63;
+    L.oTI = o; o += W + 63;
+  }
+  if (dt) {
+    L.oWH = o; o += W + 1;
+    L.oEX = o; o += kMaxWaves * kWave;
+    L.oEXS = o; o += kMaxWaves;
+    L.oEX2 = o; o += kMaxWaves * kWave;
+    L.oEXS2 = o; o += kMaxWaves;
+  }
+  L.words = o;
+  return L;
+}
+
+enum HMode { kSums = 0, kCost = 1, kCostHPair = 2, kHPair = 3 };
+
+struct HArgs {
+  const uint8_t* left;
+  const uint8_t* right;
+  const uint8_t* guide;
+  int pitch, W, H, D;
+  float inv_sigma_s, range_coef, out_scale;
+  void* vol;
+  int32_t* s_rt;
+  int32_t* s_l;
+  int32_t* s_ll;
+  int32_t* s_t;
+  int32_t* s_tt;
+  int8_t* ex;      // FP16 working volume: per-(pixel, 64-d chunk) exponent map, else NULL
+  int segl, nw;
+};
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
+
+// DT weight between G(a) and its predecessor G(b): exp(-1/sigma_s - |G(a)-G(b)| / (255 sigma_r)).
+__device__ __forceinline__ float dt_weight(int ga, int gb, float inv_sigma_s, float range_coef) {
+  return expf(-(inv_sigma_s + (float)abs(ga - gb) * range_coef));
+}
+
+// Stage the packed window columns and the per-position window statistics of
+// both images for row y and disparity chunk d0 (reads the 2R+1 image rows once).
+template <int R>
+__device__ void stage_zncc(const HArgs& a, const HLayout& lay, uint32_t* smem, int y, int d0, int mode) {
+  constexpr int NP = packs_of(R);
+  constexpr int N = (2 * R + 1) * (2 * R + 1);
+  const int tid = threadIdx.x, nt = blockDim.x, W = a.W, H = a.H;
+  uint32_t* LP = smem + lay.oLP;
+  uint32_t* TP = smem + lay.oTP;
+  int rows_off[NP * 4];
+#pragma unroll
+  for (int q = 0; q < NP * 4; ++q) rows_off[q] = (q < 2 * R + 1) ? clampi(y - R + q, 0, H - 1) * a.pitch : -1;
+  for (int i = tid; i < lay.nLP; i += nt) {
+    const int col = clampi(i - R, 0, W - 1);
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      uint32_t p = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (rows_off[4 * k + j] >= 0) p |= (uint32_t)a.left[rows_off[4 * k + j] + col] << (8 * j);
+      LP[k * lay.nLP + i] = p;
+    }
+  }
+  for (int i = tid; i < lay.nTP; i += nt) {
+    const int col = clampi(i - 63 - R - d0, 0, W - 1);
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      uint32_t p = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (rows_off[4 * k + j] >= 0) p |= (uint32_t)a.right[rows_off[4 * k + j] + col] << (8 * j);
+      TP[k * lay.nTP + i] = p;
+    }
+  }
+  __syncthreads();
+  int32_t* LS = (int32_t*)(smem + lay.oLS);
+  float* LI = (float*)(smem + lay.oLI);
+  int32_t* TS = (int32_t*)(smem + lay.oTS);
+  float* TI = (float*)(smem + lay.oTI);
+  // reference statistics at x: columns x-R..x+R are LP entries x .. x+2R
+  for (int x = tid; x < W; x += nt) {
+    uint32_t s = 0, ss = 0;
+#pragma unroll
+    for (int i = 0; i <= 2 * R; ++i)
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        const uint32_t p = LP[k * lay.nLP + x + i];
+        s = __builtin_amdgcn_udot4(p, 0x01010101u, s, false);
+        ss = __builtin_amdgcn_udot4(p, p, ss, false);
+      }
+    const int v = (int)(__umul24(N, ss) - __umul24(s, s));
+    LS[x] = (int)s;
+    LI[x] = v > 0 ? 1.0f / sqrtf((float)v) : 0.0f;
+    if (mode == kSums && blockIdx.x == 0) {
+      if (a.s_l) a.s_l[(size_t)y * W + x] = (int)s;
+      if (a.s_ll) a.s_ll[(size_t)y * W + x] = (int)ss;
+    }
+  }
+  // target statistics at x' = t - 63 - d0: columns x'-R..x'+R are TP entries t .. t+2R
+  for (int t = tid; t < W + 63; t += nt) {
+    uint32_t s = 0, ss = 0;
+#pragma unroll
+    for (int i = 0; i <= 2 * R; ++i)
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        const uint32_t p = TP[k * lay.nTP + t + i];
+        s = __builtin_amdgcn_udot4(p, 0x01010101u, s, false);
+        ss = __builtin_amdgcn_udot4(p, p, ss, false);
+      }
+    const int v = (int)(__umul24(N, ss) - __umul24(s, s));
+    TS[t] = (int)s;
+    TI[t] = v > 0 ? 1.0f / sqrtf((float)v) : 0.0f;
+    if (mode == kSums) {
+      // each x' in [-(D-1), W-1] is written by exactly one chunk
+      const int xe = t - 63 - d0;
+      const bool own = (blockIdx.x == 0) ? (xe >= -63) : (xe <= -d0);
+      if (own && xe >= -(a.D - 1) && xe <= W - 1) {
+        const size_t idx = (size_t)y * (W + a.D - 1) + xe + a.D - 1;
+        if (a.s_t) a.s_t[idx] = (int)s;
+        if (a.s_tt) a.s_tt[idx] = (int)ss;
+      }
+    }
+  }
+}
+
+// W_L(x) of row y for x in [0, W]; zero at both ends.
+__device__ void stage_row_weights(const HArgs& a, float* WH, int y) {
+  const uint8_t* g = a.guide + (size_t)y * a.pitch;
+  for (int x = threadIdx.x; x <= a.W; x += blockDim.x)
+    WH[x] = (x >= 1 && x < a.W) ? dt_weight(g[x], g[x - 1], a.inv_sigma_s, a.range_coef) : 0.0f;
+}
+
+// Cross-sum column at column p for this lane's disparity: sum_k dot4(L pack, T pack).
+template <int R>
+__device__ __forceinline__ uint32_t colsum(const uint32_t* LP, const uint32_t* TP, int nLP, int nTP, int p,
+                                           int lane) {
+  constexpr int NP = packs_of(R);
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) s = __builtin_amdgcn_udot4(LP[k * nLP + p + R], TP[k * nTP + p + R + 63 - lane], s, false);
+  return s;
+}
+
+// cost = 1 - clamp(ZNCC, -1, 1) from the exact integer numerator l^2 S_RT - S_R S_T.
+__device__ __forceinline__ float zncc_cost_from(uint32_t srt, int sl, float il, int st, float it, int N) {
+  const int num = (int)(__umul24((uint32_t)N, srt) - __umul24((uint32_t)sl, (uint32_t)st));
+  const float c = fmaf(-(float)num, il * it, 1.0f);
+  return fminf(fmaxf(c, 0.0f), 2.0f);
+}
+
+// ---------------------------------------------------------------------------
+// Narrow working volumes.  An FP16 working volume (ex != NULL) stores each
+// (pixel, chunk of 64 disparities) with a shared power-of-two exponent e:
+// value = fp16 * 2^(e - 14).  The exponent is chosen from the chunk's maximum so
+// that the largest value lands in [2^14, 2^15); rescaling by a power of two is
+// exact, so only the FP16 rounding remains.  Without it the DT's gain, which
+// ranges from ~1 at edges to 1/(1-K) per pass in flat areas, pushes values out
+// of FP16's range.  BF16 and FP32 volumes store plain values.
+// ---------------------------------------------------------------------------
+constexpr int kExpBias = 14;
+
+// Maximum of a non-negative 32-bit key over the 64 lanes (result from lane 63).
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));  // row_mirror
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Exponent of the largest |v| of the wave (0 when every value is 0).
+__device__ __forceinline__ int wave_exponent(float v) {
+  const uint32_t m = wave_max_u32(__float_as_uint(v) & 0x7FFFFFFFu);
+  return m ? (int)(m >> 23) - 127 : 0;
+}
+
+template <typename T>
+__device__ __forceinline__ float load_scaled(const T* p, float scale) {
+  return Elem<T>::load(p) * scale;
+}
+
+template <int R, int SEG, typename T, int MODE>
+__global__ __launch_bounds__(1024) void hpass_kernel(HArgs a) {
+  extern __shared__ uint32_t smem[];
+  constexpr int NW = 2 * R + 1;  // window side
+  constexpr int N = NW * NW;
+  constexpr bool kZncc = MODE != kHPair;
+  constexpr bool kDT = MODE == kCostHPair || MODE == kHPair;
+  constexpr bool kHalf = std::is_same<T, _Float16>::value;
+  const int y = blockIdx.y, d0 = blockIdx.x * kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int d = d0 + lane;
+  const bool active = d < a.D;
+  const int dl = active ? d : a.D - 1;  // loads of idle lanes read a valid element
+  const int W = a.W;
+  const HLayout lay = h_layout(W, R, kZncc, kDT);
+  if constexpr (kZncc) stage_zncc<R>(a, lay, smem, y, d0, MODE);
+  if constexpr (kDT) stage_row_weights(a, (float*)(smem + lay.oWH), y);
+  __syncthreads();
+
+  const int x0 = wave * a.segl;
+  const int len = min(a.segl, W - x0);  // >= 1, wave-uniform
+  const size_t rowbase = (size_t)y * W * a.D;
+  T* vol = (T*)a.vol;
+
+  const uint32_t* LP = smem + lay.oLP;
+  const uint32_t* TP = smem + lay.oTP;
+  const int32_t* LS = (const int32_t*)(smem + lay.oLS);
+  const float* LI = (const float*)(smem + lay.oLI);
+  const int32_t* TS = (const int32_t*)(smem + lay.oTS);
+  const float* TI = (const float*)(smem + lay.oTI);
+
+  if constexpr (MODE == kSums || MODE == kCost) {
+    if (MODE == kSums && a.s_rt == nullptr) return;
+    // running window: ring[s] holds the column sums of columns x0-R+s (mod NW)
+    uint32_t ring[NW];
+    uint32_t S = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      ring[i] = colsum<R>(LP, TP, lay.nLP, lay.nTP, x0 - R + i, lane);
+      S += ring[i];
+    }
+    for (int kb = 0; kb < len; kb += NW) {
+#pragma unroll
+      for (int u = 0; u < NW; ++u) {
+        const int k = kb + u;
+        if (k < len) {
+          const int x = x0 + k;
+          if (k > 0) {
+            const int slot = (u + NW - 1) % NW;
+            const uint32_t cn = colsum<R>(LP, TP, lay.nLP, lay.nTP, x + R, lane);
+            S = S + cn - ring[slot];
+            ring[slot] = cn;
+          }
+          if (active) {
+            const size_t idx = rowbase + (size_t)x * a.D + d;
+            if constexpr (MODE == kSums) {
+              a.s_rt[idx] = (int32_t)S;
+            } else {
+              const float c = zncc_cost_from(S, LS[x], LI[x], TS[x + 63 - lane], TI[x + 63 - lane], N);
+              Elem<T>::store(vol + idx, c * a.out_scale);
+            }
+          }
+        }
+      }
+    }
+    return;
+  } else {
+    const float* WH = (const float*)(smem + lay.oWH);
+    float* EX = (float*)(smem + lay.oEX);
+    float* EXS = (float*)(smem + lay.oEXS);
+    float* EX2 = (float*)(smem + lay.oEX2);
+    float* EXS2 = (float*)(smem + lay.oEXS2);
+    const bool scaled = kHalf && a.ex != nullptr;
+    const int nck = (a.D + kWave - 1) / kWave;
+    int8_t* exrow = scaled ? a.ex + (size_t)y * W * nck + blockIdx.x : nullptr;
+    float c[SEG];
+    // ---- loop A: values of the segment + carry-free L pass (ell) and weight product P
+    float ell = 0.0f, P = 1.0f;
+    if constexpr (MODE == kCostHPair) {
+      uint32_t ring[NW];
+      uint32_t S = 0;
+#pragma unroll
+      for (int i = 0; i < NW; ++i) {
+        ring[i] = colsum<R>(LP, TP, lay.nLP, lay.nTP, x0 - R + i, lane);
+        S += ring[i];
+      }
+#pragma unroll
+      for (int k = 0; k < SEG; ++k) {
+        const bool in = k < len;
+        const int x = x0 + (in ? k : len - 1);
+        if (k > 0) {
+          const int slot = (k - 1) % NW;
+          const uint32_t cn = colsum<R>(LP, TP, lay.nLP, lay.nTP, x + R, lane);
+          S = S + cn - ring[slot];
+          ring[slot] = cn;
+        }
+        c[k] = zncc_cost_from(S, LS[x], LI[x], TS[x + 63 - lane], TI[x + 63 - lane], N);
+        const float w = WH[x];
+        ell = in ? fmaf(w, ell, c[k]) : ell;
+        P = in ? P * w : P;
+      }
+    } else {
+      const T* src = vol + rowbase + (size_t)x0 * a.D + dl;
+#pragma unroll
+      for (int k = 0; k < SEG; ++k) {
+        const int kk = k < len ? k : len - 1;
+        c[k] = Elem<T>::load(src + (size_t)kk * a.D);
+      }
+      if (scaled) {
+#pragma unroll
+        for (int k = 0; k < SEG; ++k) {
+          const int kk = k < len ? k : len - 1;
+          c[k] = ldexpf(c[k], (int)exrow[(size_t)(x0 + kk) * nck] - kExpBias);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < SEG; ++k) {
+        const bool in = k < len;
+        const float w = WH[x0 + (in ? k : len - 1)];
+        ell = in ? fmaf(w, ell, c[k]) : ell;
+        P = in ? P * w : P;
+      }
+    }
+    EX[wave * kWave + lane] = ell;
+    if (lane == 0) EXS[wave] = P;
+    __syncthreads();
+    float carry = 0.0f;
+    for (int s = 0; s < wave; ++s) carry = fmaf(EXS[s], carry, EX[s * kWave + lane]);
+    // ---- loop B: exact L pass from the true carry; accumulate the carry-free R value at x0
+    float prev = carry, acc = 0.0f, pi = 1.0f;
+#pragma unroll
+    for (int k = 0; k < SEG; ++k) {
+      const bool in = k < len;
+      const float w = WH[x0 + (in ? k : len - 1)];
+      const float cl = fmaf(w, prev, c[k]);
+      c[k] = in ? cl : c[k];
+      prev = in ? cl : prev;
+      if (k > 0) pi = in ? pi * w : pi;
+      acc = in ? fmaf(cl, pi, acc) : acc;
+    }
+    const float Q = pi * WH[x0 + len];
+    EX2[wave * kWave + lane] = acc;
+    if (lane == 0) EXS2[wave] = Q;
+    __syncthreads();
+    float kappa = 0.0f;
+    for (int s = a.nw - 1; s > wave; --s) kappa = fmaf(EXS2[s], kappa, EX2[s * kWave + lane]);
+    // ---- loop D: exact R pass from the true carry, then store
+    float next = kappa;
+#pragma unroll
+    for (int k = SEG - 1; k >= 0; --k) {
+      const bool in = k < len;
+      const float cr = fmaf(WH[x0 + (in ? k + 1 : len)], next, c[k]);
+      c[k] = in ? cr : c[k];
+      next = in ? cr : next;
+    }
+    T* dst = vol + rowbase + (size_t)x0 * a.D + d;
+#pragma unroll
+    for (int k = 0; k < SEG; ++k) {
+      if (k < len) {
+        float v = c[k] * a.out_scale;
+        if (scaled) {
+          const int e = wave_exponent(active ? v : 0.0f);
+          v = ldexpf(v, kExpBias - e);
+          if (lane == 0) exrow[(size_t)(x0 + k) * nck] = (int8_t)e;
+        }
+        if (active) Elem<T>::store(dst + (size_t)k * a.D, v);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// V pair (+ optional WTA)
+// ---------------------------------------------------------------------------
+struct VArgs {
+  const uint8_t* guide;
+  int pitch, W, H, D;
+  float inv_sigma_s, range_coef, out_scale;
+  void* vol;
+  int8_t* ex;          // FP16 working volume exponent map (see above), else NULL
+  int32_t* disp;       // WTA with a single chunk: final disparity
+  float* part_val;     // WTA with several chunks: [chunk][H][W] minimum
+  int32_t* part_idx;   // and its disparity
+  int segl, nw;
+};
+
+__host__ __device__ inline int v_lds_words(int H, int DPL) { return (H + 1) + 2 * (kMaxWaves * kWave * DPL + kMaxWaves); }
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off));
+  return v;
+}
+
+template <int SEG, typename T, int DPL, bool WTA>
+__global__ __launch_bounds__(1024) void vpass_kernel(VArgs a) {
+  extern __shared__ uint32_t smem[];
+  constexpr bool kHalf = std::is_same<T, _Float16>::value;
+  const int chunk = blockIdx.x, x = blockIdx.y;
+  const int d0 = chunk * kWave * DPL;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int W = a.W, H = a.H, D = a.D;
+  float* WV = (float*)smem;
+  float* EX = WV + (H + 1);
+  float* EXS = EX + kMaxWaves * kWave * DPL;
+  float* EX2 = EXS + kMaxWaves;
+  float* EXS2 = EX2 + kMaxWaves * kWave * DPL;
+  for (int y = threadIdx.x; y <= H; y += blockDim.x)
+    WV[y] = (y >= 1 && y < H) ? dt_weight(a.guide[(size_t)y * a.pitch + x], a.guide[(size_t)(y - 1) * a.pitch + x],
+                                          a.inv_sigma_s, a.range_coef)
+                              : 0.0f;
+  __syncthreads();
+  const int y0 = wave * a.segl;
+  const int len = min(a.segl, H - y0);  // >= 1, wave-uniform
+  const size_t rowstride = (size_t)W * D;
+  T* vol = (T*)a.vol;
+  const bool scaled = kHalf && a.ex != nullptr;
+  const int nck = (D + kWave - 1) / kWave;
+  bool act[DPL];
+  int dl[DPL];
+#pragma unroll
+  for (int j = 0; j < DPL; ++j) {
+    act[j] = d0 + lane + kWave * j < D;
+    dl[j] = act[j] ? d0 + lane + kWave * j : D - 1;
+  }
+
+  float c[DPL][SEG];
+#pragma unroll
+  for (int j = 0; j < DPL; ++j) {
+    const T* src = vol + (size_t)y0 * rowstride + (size_t)x * D + dl[j];
+#pragma unroll
+    for (int k = 0; k < SEG; ++k) {
+      const int kk = k < len ? k : len - 1;
+      c[j][k] = Elem<T>::load(src + (size_t)kk * rowstride);
+    }
+  }
+  if (scaled) {
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) {
+      if (chunk * DPL + j >= nck) continue;  // no disparity of this lane group exists
+      const int8_t* ex = a.ex + (size_t)y0 * W * nck + (size_t)x * nck + chunk * DPL + j;
+#pragma unroll
+      for (int k = 0; k < SEG; ++k) {
+        const int kk = k < len ? k : len - 1;
+        c[j][k] = ldexpf(c[j][k], (int)ex[(size_t)kk * W * nck] - kExpBias);
+      }
+    }
+  }
+  // ---- loop A: carry-free U pass
+  float ell[DPL], P = 1.0f;
+#pragma unroll
+  for (int j = 0; j < DPL; ++j) ell[j] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < SEG; ++k) {
+    const bool in = k < len;
+    const float w = WV[y0 + (in ? k : len - 1)];
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) ell[j] = in ? fmaf(w, ell[j], c[j][k]) : ell[j];
+    P = in ? P * w : P;
+  }
+#pragma unroll
+  for (int j = 0; j < DPL; ++j) EX[(wave * DPL + j) * kWave + lane] = ell[j];
+  if (lane == 0) EXS[wave] = P;
+  __syncthreads();
+  float prev[DPL];
+#pragma unroll
+  for (int j = 0; j < DPL; ++j) {
+    float carry = 0.0f;
+    for (int s = 0; s < wave; ++s) carry = fmaf(EXS[s], carry, EX[(s * DPL + j) * kWave + lane]);
+    prev[j] = carry;
+  }
+  // ---- loop B: exact U pass; carry-free D value at y0
+  float acc[DPL], pi = 1.0f;
+#pragma unroll
+  for (int j = 0; j < DPL; ++j) acc[j] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < SEG; ++k) {
+    const bool in = k < len;
+    const float w = WV[y0 + (in ? k : len - 1)];
+    if (k > 0) pi = in ? pi * w : pi;
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) {
+      const float cu = fmaf(w, prev[j], c[j][k]);
+      c[j][k] = in ? cu : c[j][k];
+      prev[j] = in ? cu : prev[j];
+      acc[j] = in ? fmaf(cu, pi, acc[j]) : acc[j];
+    }
+  }
+  const float Q = pi * WV[y0 + len];
+#pragma unroll
+  for (int j = 0; j < DPL; ++j) EX2[(wave * DPL + j) * kWave + lane] = acc[j];
+  if (lane == 0) EXS2[wave] = Q;
+  __syncthreads();
+  float next[DPL];
+#pragma unroll
+  for (int j = 0; j < DPL; ++j) {
+    float kappa = 0.0f;
+    for (int s = a.nw - 1; s > wave; --s) kappa = fmaf(EXS2[s], kappa, EX2[(s * DPL + j) * kWave + lane]);
+    next[j] = kappa;
+  }
+  // ---- loop D: exact D pass
+#pragma unroll
+  for (int k = SEG - 1; k >= 0; --k) {
+    const bool in = k < len;
+    const float w = WV[y0 + (in ? k + 1 : len)];
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) {
+      const float cd = fmaf(w, next[j], c[j][k]);
+      c[j][k] = in ? cd : c[j][k];
+      next[j] = in ? cd : next[j];
+    }
+  }
+  if constexpr (!WTA) {
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) {
+      T* dst = vol + (size_t)y0 * rowstride + (size_t)x * D + d0 + lane + kWave * j;
+      int8_t* ex = scaled ? a.ex + (size_t)y0 * W * nck + (size_t)x * nck + chunk * DPL + j : nullptr;
+#pragma unroll
+      for (int k = 0; k < SEG; ++k)
+        if (k < len) {
+          float v = c[j][k] * a.out_scale;
+          if (scaled) {
+            const int e = wave_exponent(act[j] ? v : 0.0f);
+            v = ldexpf(v, kExpBias - e);
+            if (lane == 0) ex[(size_t)k * W * nck] = (int8_t)e;
+          }
+          if (act[j]) Elem<T>::store(dst + (size_t)k * rowstride, v);
+        }
+    }
+  } else {
+    // argmin over the chunk's disparities, lowest d on ties (Eq. WTA1)
+    const float inf = __builtin_inff();
+#pragma unroll
+    for (int k = 0; k < SEG; ++k)
+      if (k < len) {
+        float v[DPL];
+        float best = inf;
+#pragma unroll
+        for (int j = 0; j < DPL; ++j) {
+          v[j] = act[j] ? c[j][k] : inf;
+          best = fminf(best, v[j]);
+        }
+        const float m = wave_min(best);
+        int dbest = 0;
+#pragma unroll
+        for (int j = DPL - 1; j >= 0; --j) {
+          const unsigned long long mask = __ballot(v[j] == m);
+          if (mask) dbest = d0 + kWave * j + __builtin_ctzll(mask);
+        }
+        if (lane == 0) {
+          const size_t p = (size_t)(y0 + k) * W + x;
+          if (a.disp) {
+            a.disp[p] = dbest;
+          } else {
+            a.part_val[(size_t)chunk * W * H + p] = m;
+            a.part_idx[(size_t)chunk * W * H + p] = dbest;
+          }
+        }
+      }
+  }
+}
+
+// Combine per-chunk minima (chunks in increasing d; strict < keeps the lowest d).
+static __global__ void wta_combine_kernel(const float* part_val, const int32_t* part_idx, int nchunks, int npix,
+                                          int32_t* disp) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npix) return;
+  float best = part_val[p];
+  int idx = part_idx[p];
+  for (int c = 1; c < nchunks; ++c) {
+    const float v = part_val[(size_t)c * npix + p];
+    if (v < best) {
+      best = v;
+      idx = part_idx[(size_t)c * npix + p];
+    }
+  }
+  disp[p] = idx;
+}
+
+// Standalone WTA: each wave takes pixels p = global wave id, + total waves, ...
+template <typename T>
+__global__ __launch_bounds__(256) void wta_kernel(const T* vol, int npix, int D, int32_t* disp) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int gw = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int nwaves = gridDim.x * blockDim.x / kWave;
+  const float inf = __builtin_inff();
+  for (int p = gw; p < npix; p += nwaves) {
+    const T* c = vol + (size_t)p * D;
+    float best = inf;
+    int bd = 0;
+    for (int dd = lane; dd < D; dd += kWave) {
+      const float v = Elem<T>::load(c + dd);
+      if (v < best) {
+        best = v;
+        bd = dd;
+      }
+    }
+    const float m = wave_min(best);
+    // among the lanes holding the minimum, the smallest of their own first d
+    int cand = (best == m) ? bd : 0x7fffffff;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) cand = min(cand, __shfl_xor(cand, off));
+    if (lane == 0) disp[p] = cand;
+  }
+}
+
+}  // namespace zdt

@@ -1,0 +1,52 @@
+// zdt_host.hpp -- host-side helpers shared by the C-ABI translation unit and
+// the per-dtype kernel-instance translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "zdt.h"
+#include "zdt_device.hpp"
+
+namespace zdt {
+
+// Record an error message for zdt_last_error() and return `code`.
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+
+// Per-launch event timing (active between zdt_profile_enable(1) and (0)).
+struct ProfRec {
+  const char* name;
+  hipEvent_t start, stop;
+};
+bool prof_begin(ProfRec& rec, hipStream_t s);
+void prof_end(ProfRec& rec, hipStream_t s);
+
+template <typename Kernel, typename... A>
+int launch(const char* name, Kernel kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, A... args) {
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return fail(ZDT_EHIP, "%s: cannot reserve %zu B of LDS: %s", name, lds, hipGetErrorString(e));
+  }
+  ProfRec rec{name, nullptr, nullptr};
+  const bool prof = prof_begin(rec, s);
+  hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+  hipError_t e = hipGetLastError();
+  if (prof) prof_end(rec, s);
+  if (e != hipSuccess) return fail(ZDT_EHIP, "%s: launch failed: %s", name, hipGetErrorString(e));
+  return ZDT_OK;
+}
+
+// Segment lengths (values per lane) compiled for the H and V passes.
+constexpr int kHSegs[] = {20, 40, 80};
+constexpr int kVSegs[] = {8, 12, 24, 48, 72};
+constexpr int kNumHSegs = 3, kNumVSegs = 5;
+
+// Kernel dispatch, one set per volume element type (defined in zdt_inst_*.hip).
+#define ZDT_DECLARE_DISPATCH(SUFFIX)                                                                      \
+  int dispatch_h_##SUFFIX(int mode, int R, int seg, const HArgs& a, hipStream_t s);                     \
+  int dispatch_v_##SUFFIX(int seg, int dpl, bool wta, const VArgs& a, int nchunks, hipStream_t s);     \
+  int dispatch_wta_##SUFFIX(const void* vol, int npix, int D, int32_t* disp, hipStream_t s);
+ZDT_DECLARE_DISPATCH(f32)
+ZDT_DECLARE_DISPATCH(f16)
+ZDT_DECLARE_DISPATCH(bf16)
+#undef ZDT_DECLARE_DISPATCH
+
+}  // namespace zdt

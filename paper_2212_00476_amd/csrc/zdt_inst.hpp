@@ -1,0 +1,98 @@
+// zdt_inst.hpp -- kernel instances and dispatch for one volume element type.
+// Included once by each zdt_inst_<type>.hip with ZDT_ELEM and ZDT_SUFFIX set.
+#pragma once
+#include <type_traits>
+
+#include "zdt_host.hpp"
+
+namespace zdt {
+namespace inst {
+
+template <int R, int SEG, typename T, int MODE>
+int run_h(const HArgs& a, hipStream_t s) {
+  const HLayout lay = h_layout(a.W, R, MODE != kHPair, MODE == kCostHPair || MODE == kHPair);
+  static const char* const names[] = {"zncc_sums", "zncc_cost", "zncc_hpair", "dt_hpair"};
+  return launch(names[MODE], hpass_kernel<R, SEG, T, MODE>, dim3((a.D + kWave - 1) / kWave, a.H),
+                dim3(kWave * a.nw), (size_t)lay.words * 4, s, a);
+}
+
+template <int R, typename T, int MODE>
+int run_h_seg(int seg, const HArgs& a, hipStream_t s) {
+  switch (seg) {
+    case 20: return run_h<R, 20, T, MODE>(a, s);
+    case 40: return run_h<R, 40, T, MODE>(a, s);
+    case 80: return run_h<R, 80, T, MODE>(a, s);
+  }
+  return fail(ZDT_EUNSUPPORTED, "no H-pass instance for segment length %d", seg);
+}
+
+// Streaming modes (sums, raw cost) keep no per-segment registers: SEG = 0.
+template <typename T, int MODE>
+int run_h_radius(int R, int seg, const HArgs& a, hipStream_t s) {
+  constexpr bool stream = MODE == kSums || MODE == kCost;
+  switch (R) {
+#define ZDT_CASE(RR)                               \
+  case RR:                                         \
+    if constexpr (stream) return run_h<RR, 0, T, MODE>(a, s); \
+    else return run_h_seg<RR, T, MODE>(seg, a, s);
+    ZDT_CASE(0) ZDT_CASE(1) ZDT_CASE(2) ZDT_CASE(3) ZDT_CASE(4) ZDT_CASE(5) ZDT_CASE(6)
+#undef ZDT_CASE
+  }
+  return fail(ZDT_EUNSUPPORTED, "no H-pass instance for radius %d", R);
+}
+
+template <int SEG, typename T, int DPL, bool WTA>
+int run_v(const VArgs& a, int nchunks, hipStream_t s) {
+  return launch(WTA ? "dt_vpair_wta" : "dt_vpair", vpass_kernel<SEG, T, DPL, WTA>, dim3(nchunks, a.W),
+                dim3(kWave * a.nw), (size_t)v_lds_words(a.H, DPL) * 4, s, a);
+}
+
+template <typename T, int DPL, bool WTA>
+int run_v_seg(int seg, const VArgs& a, int nchunks, hipStream_t s) {
+  switch (seg) {
+    case 8: return run_v<8, T, DPL, WTA>(a, nchunks, s);
+    case 12: return run_v<12, T, DPL, WTA>(a, nchunks, s);
+    case 24: return run_v<24, T, DPL, WTA>(a, nchunks, s);
+    case 48: return run_v<48, T, DPL, WTA>(a, nchunks, s);
+    case 72: return run_v<72, T, DPL, WTA>(a, nchunks, s);
+  }
+  return fail(ZDT_EUNSUPPORTED, "no V-pass instance for segment length %d", seg);
+}
+
+}  // namespace inst
+}  // namespace zdt
+
+#define ZDT_CAT2(a, b) a##b
+#define ZDT_CAT(a, b) ZDT_CAT2(a, b)
+
+namespace zdt {
+
+int ZDT_CAT(dispatch_h_, ZDT_SUFFIX)(int mode, int R, int seg, const HArgs& a, hipStream_t s) {
+  using T = ZDT_ELEM;
+  switch (mode) {
+    case kCost: return inst::run_h_radius<T, kCost>(R, seg, a, s);
+    case kCostHPair: return inst::run_h_radius<T, kCostHPair>(R, seg, a, s);
+    case kHPair: return inst::run_h_seg<0, T, kHPair>(seg, a, s);
+    case kSums:
+      if constexpr (std::is_same<T, float>::value) return inst::run_h_radius<T, kSums>(R, seg, a, s);
+      break;
+  }
+  return fail(ZDT_EUNSUPPORTED, "no H-pass instance for mode %d", mode);
+}
+
+int ZDT_CAT(dispatch_v_, ZDT_SUFFIX)(int seg, int dpl, bool wta, const VArgs& a, int nchunks, hipStream_t s) {
+  using T = ZDT_ELEM;
+  if (!wta) return inst::run_v_seg<T, 1, false>(seg, a, nchunks, s);
+  if (dpl == 2) return inst::run_v_seg<T, 2, true>(seg, a, nchunks, s);
+  return inst::run_v_seg<T, 1, true>(seg, a, nchunks, s);
+}
+
+int ZDT_CAT(dispatch_wta_, ZDT_SUFFIX)(const void* vol, int npix, int D, int32_t* disp, hipStream_t s) {
+  using T = ZDT_ELEM;
+  const int threads = 256, waves_per_block = threads / kWave;
+  int blocks = (npix + waves_per_block - 1) / waves_per_block;
+  if (blocks > 8192) blocks = 8192;
+  return launch("wta", wta_kernel<T>, dim3(blocks), dim3(threads), 0, s, (const T*)vol, npix, D, disp);
+}
+
+}  // namespace zdt

@@ -1,0 +1,79 @@
+"""The C-ABI library loads on the CPU, exports every entry point declared in
+include/zdt.h, and rejects bad arguments before touching the device."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+import paper_2212_00476_amd as zdt
+from paper_2212_00476_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = []
+    for f in os.listdir(os.path.join(ROOT, "include")):
+        if f.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", f)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names += re.findall(r"^[A-Za-z_][\w\s\*]*?\b(\w+)\s*\([^;{]*\)\s*;", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    declared = _declared_functions()
+    assert len(declared) >= 11, declared
+    missing = [n for n in declared if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(_lib.EXPORTED) == set(declared)
+
+
+def _rc_of(fn, *args):
+    try:
+        fn(*args)
+    except zdt.ZdtError as e:
+        return e.code
+    return 0
+
+
+def test_argument_validation_without_device():
+    lib = zdt.load()
+    good = zdt.params(64, 32, 16)
+    assert zdt.volume_size(good) == 64 * 32 * 16 * 4
+    assert zdt.volume_size(zdt.params(64, 32, 16, vol_dtype=zdt.ZDT_F16)) == 64 * 32 * 16 * 2
+    assert zdt.workspace_size(good) == 0
+    bad = [
+        zdt.params(0, 32, 16),
+        zdt.params(64, 32, 0),
+        zdt.params(64, 32, 16, radius=-1),
+        zdt.params(64, 32, 16, sigma_s=0.0),
+        zdt.params(64, 32, 16, sigma_r=-1.0),
+        zdt.params(64, 32, 16, sigma_r=math.nan),
+        zdt.params(64, 32, 16, dt_iters=-1),
+        zdt.params(64, 32, 16, vol_dtype=7),
+        zdt.params(64, 32, 16, flags=8),
+        zdt.params(64, 32, 16, pitch=10),
+    ]
+    for p in bad:
+        assert zdt.volume_size(p) == 0
+        rc = lib.stereo_solve(ctypes.byref(p), None, None, None, None, None, None)
+        assert rc == _lib.ZDT_EINVAL, (p.width, p.max_disp, rc)
+        assert lib.zdt_last_error().decode()
+    # valid parameters but NULL device pointers: rejected synchronously
+    assert lib.stereo_solve(ctypes.byref(good), None, None, None, None, None, None) == _lib.ZDT_EINVAL
+    assert lib.zncc_cost_volume(ctypes.byref(good), None, None, None, None) == _lib.ZDT_EINVAL
+    assert lib.dt_aggregate(ctypes.byref(good), None, None, None, None) == _lib.ZDT_EINVAL
+    assert lib.wta_disparity(ctypes.byref(good), None, None, None) == _lib.ZDT_EINVAL
+    # outside this build's limits
+    for p in (zdt.params(64, 32, 16, radius=7), zdt.params(4000, 32, 16), zdt.params(64, 4000, 16)):
+        assert lib.stereo_solve(ctypes.byref(p), None, None, None, None, None, None) == _lib.ZDT_EUNSUPPORTED
+
+
+def test_reserved_fields_must_be_zero():
+    p = zdt.params(64, 32, 16)
+    p.reserved[2] = 1
+    assert zdt.volume_size(p) == 0

@@ -60,6 +60,8 @@ def test_cross_sums_match_box_filter_of_products(H, W, D, r):
     for d in range(D):
         prod = Lp * Rp[:, D - 1 - d:D - 1 - d + W + 2 * r]
         assert np.array_equal(S[:, :, d], _box_sum_integral(prod, r)), d
+    for (x, y, d) in [(0, 0, 0), (W - 1, H - 1, D - 1), (3, 2, 4), (W // 2, H // 2, 1)]:
+        assert oracle.cross_sum_at(L, R, r, x, y, d) == S[y, x, d]
 
 
 def test_cross_sums_incremental_identities():

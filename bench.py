@@ -95,6 +95,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-slices", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the whole pair on a single MI355X "
@@ -111,6 +113,14 @@ def main():
     L = torch.from_numpy(pr.left).to(dev)
     Rt = torch.from_numpy(pr.right).to(dev)
     nvol = W * H * D
+
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     forms = {}
     solvers = {}

@@ -1,7 +1,8 @@
 // zdt_device.hpp -- gfx950 kernels of the stereo hot path.
 //
-//   hpass_kernel   one workgroup per (row y, chunk of 64 disparities); lanes map
-//                  to d, each wave owns one contiguous x-segment of the row.
+//   hpass_kernel   one workgroup per (row y, chunk of LPS disparities); lanes map
+//                  to d, each group of LPS lanes owns one contiguous x-segment of
+//                  the row (LPS = 64: one segment per wave; LPS = 32: two).
 //                  Modes: the exact int32 cross sums, the ZNCC cost (Sec. III-A,
 //                  Eq. OP_ZNCC), the cost fused with the L and R passes
 //                  (Eqs. DT1-DT2), or the L and R passes over a stored volume.
@@ -11,13 +12,20 @@
 //                  of Eq. WTA1 so that the last volume is never written.
 //   wta_kernel     standalone WTA over a stored volume; one wave per pixel.
 //
-// A line (a row for H, a column for V) is split into one segment per wave.
-// Every pass is a first-order linear recursion c[i] += w[i] * c[i-1], so a
-// segment's result is its carry-free local result plus (product of its
-// weights) x (carry in).  The carries are composed across the segments of the
-// workgroup through LDS, then each segment re-runs its recursion from the true
-// carry: the values written are the sequential recursion of the paper, apart
-// from the rounding of the carries.
+// A line (a row for H, a column for V) is split into segments.  Every pass is a
+// first-order linear recursion c[i] += w[i] * c[i-1], so a segment's result is
+// its carry-free local result plus (product of its weights) x (carry in).  The
+// carries are composed across the segments of the workgroup through LDS, then
+// each segment re-runs its recursion from the true carry: the values written
+// are the sequential recursion of the paper apart from the rounding of the
+// carries.  A segment's values stay in registers between the passes, so each
+// kernel reads and writes the volume once.
+//
+// Volume accesses use raw buffer instructions: one VGPR offset per lane and the
+// per-step offset in an SGPR, every offset inside the buffer by construction, so
+// no address is kept per value.  Per-step LDS reads use one base address plus
+// immediate offsets: the LDS line arrays carry SEG entries of padding so steps
+// past a short segment need no clamping (their results are discarded).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -28,10 +36,19 @@ namespace zdt {
 
 constexpr int kWave = 64;
 constexpr int kMaxWaves = 16;
+constexpr int kMaxSegs = 32;   // segments per H workgroup (LPS = 32: two per wave)
+constexpr int kExpBias = 14;   // FP16 working volume: value = fp16 * 2^(e - kExpBias)
 
 struct bf16 {
   uint16_t bits;
 };
+
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+
+// Raw buffer over [base, base + bytes).
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
 
 template <typename T>
 struct Elem;
@@ -39,59 +56,111 @@ template <>
 struct Elem<float> {
   static __device__ __forceinline__ float load(const float* p) { return *p; }
   static __device__ __forceinline__ void store(float* p, float v) { *p = v; }
+  static __device__ __forceinline__ float bload(rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+  }
+  static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t voff, uint32_t soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, (int)soff, 0);
+  }
 };
 template <>
 struct Elem<_Float16> {
   static __device__ __forceinline__ float load(const _Float16* p) { return (float)*p; }
   static __device__ __forceinline__ void store(_Float16* p, float v) { *p = (_Float16)v; }
+  static __device__ __forceinline__ float bload(rsrc_t r, uint32_t voff, uint32_t soff) {
+    const unsigned short u = __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
+    return (float)__builtin_bit_cast(_Float16, u);
+  }
+  static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t voff, uint32_t soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)v), r, (int)voff, (int)soff,
+                                          0);
+  }
 };
 template <>
 struct Elem<bf16> {
-  static __device__ __forceinline__ float load(const bf16* p) { return __uint_as_float((uint32_t)p->bits << 16); }
-  static __device__ __forceinline__ void store(bf16* p, float v) {
+  static __device__ __forceinline__ uint16_t encode(float v) {
     uint32_t u = __float_as_uint(v);
     u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even (values are finite)
-    p->bits = (uint16_t)(u >> 16);
+    return (uint16_t)(u >> 16);
+  }
+  static __device__ __forceinline__ float load(const bf16* p) { return __uint_as_float((uint32_t)p->bits << 16); }
+  static __device__ __forceinline__ void store(bf16* p, float v) { p->bits = encode(v); }
+  static __device__ __forceinline__ float bload(rsrc_t r, uint32_t voff, uint32_t soff) {
+    const unsigned short u = __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
+    return __uint_as_float((uint32_t)u << 16);
+  }
+  static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t voff, uint32_t soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b16(encode(v), r, (int)voff, (int)soff, 0);
   }
 };
 
 __host__ __device__ constexpr int packs_of(int R) { return (2 * R + 1 + 3) / 4; }
 
+// Register discipline for the unrolled recursions.  Without it the compiler
+// issues a whole line's LDS weight reads first and sinks the (arithmetic-only)
+// recursion below them, keeping one VGPR per step live.  Every kBlock steps the
+// running values are pinned in place and memory is fenced, so each block's
+// reads are consumed before the next block's are issued.
+constexpr int kBlock = 8;
+template <typename V>
+__device__ __forceinline__ void pin1(V& v) {
+  asm volatile("" : "+v"(v));
+}
+template <typename... V>
+__device__ __forceinline__ void pin(V&... v) {
+  (pin1(v), ...);
+}
+__device__ __forceinline__ void fence() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_sched_barrier(0);
+}
+template <typename... V>
+__device__ __forceinline__ void step_fence(int k, V&... v) {
+  if (k % kBlock == kBlock - 1) {
+    pin(v...);
+    fence();
+  }
+}
+// Re-read LDS weights in each pass instead of keeping a line of them live.
+__device__ __forceinline__ void reload_fence() { asm volatile("" ::: "memory"); }
+
 // ---------------------------------------------------------------------------
-// LDS layout of hpass_kernel, in 32-bit words.
-//   LP[k][W+2R]  packed column bytes of the reference rows y-R..y+R: entry i is
-//                column clamp(i-R); byte j of pack k is row y-R+4k+j (clamped),
-//                zero past row y+R.
-//   LS, LI [W]   S_R(x) and 1/sqrt(l^2 S_RR - S_R^2) (0 for zero variance).
-//   TP[k][W+63+2R] packed target columns; entry i is column clamp(i-63-R-d0).
-//   TS, TI [W+63] target window sum and inverse deviation at x' = t-63-d0.
-//   WH[W+1]      W_L(x) for x in [0, W]; WH[0] = WH[W] = 0.
-//   EX, EX2 [16][64], EXS, EXS2 [16]   segment carries.
+// LDS layout of hpass_kernel, in 32-bit words (P = LPS - 1); every line array
+// below is followed by `pad` (= SEG) spare entries.
+//   LP[k][W+2R]   packed column bytes of the reference rows y-R..y+R: entry i is
+//                 column clamp(i-R); byte j of pack k is row y-R+4k+j (clamped),
+//                 zero past row y+R.
+//   LS, LI [W]    S_R(x) and 1/sqrt(l^2 S_RR - S_R^2) (0 for zero variance).
+//   TP[k][W+P+2R] packed target columns; entry i is column clamp(i-P-R-d0).
+//   TS, TI [W+P]  target window sum and inverse deviation at x' = t-P-d0.
+//   WH[W+1]       W_L(x) for x in [0, W]; WH[0] = WH[W] = 0.
+//   EX, EX2 [16*64], EXS, EXS2 [kMaxSegs]   segment carries.
 // ---------------------------------------------------------------------------
 struct HLayout {
-  int nLP, nTP, oLP, oLS, oLI, oTP, oTS, oTI, oWH, oEX, oEXS, oEX2, oEXS2, words;
+  int nLP, nTP, nTS, oLP, oLS, oLI, oTP, oTS, oTI, oWH, oEX, oEXS, oEX2, oEXS2, words;
 };
 
-__host__ __device__ inline HLayout h_layout(int W, int R, bool zncc, bool dt) {
+__host__ __device__ inline HLayout h_layout(int W, int R, int LPS, int pad, bool zncc, bool dt) {
   HLayout L{};
   const int NP = packs_of(R);
-  L.nLP = W + 2 * R;
-  L.nTP = W + 63 + 2 * R;
+  L.nLP = W + 2 * R + pad;
+  L.nTS = W + LPS - 1;
+  L.nTP = L.nTS + 2 * R + pad;
   int o = 0;
   if (zncc) {
     L.oLP = o; o += NP * L.nLP;
-    L.oLS = o; o += W;
-    L.oLI = o; o += W;
+    L.oLS = o; o += W + pad;
+    L.oLI = o; o += W + pad;
     L.oTP = o; o += NP * L.nTP;
-    L.oTS = o; o += W + 63;
-    L.oTI = o; o += W + 63;
+    L.oTS = o; o += L.nTS + pad;
+    L.oTI = o; o += L.nTS + pad;
   }
   if (dt) {
-    L.oWH = o; o += W + 1;
+    L.oWH = o; o += W + 1 + pad;
     L.oEX = o; o += kMaxWaves * kWave;
-    L.oEXS = o; o += kMaxWaves;
+    L.oEXS = o; o += kMaxSegs;
     L.oEX2 = o; o += kMaxWaves * kWave;
-    L.oEXS2 = o; o += kMaxWaves;
+    L.oEXS2 = o; o += kMaxSegs;
   }
   L.words = o;
   return L;
@@ -112,7 +181,7 @@ struct HArgs {
   int32_t* s_t;
   int32_t* s_tt;
   int8_t* ex;      // FP16 working volume: per-(pixel, 64-d chunk) exponent map, else NULL
-  int segl, nw;
+  int segl, nseg;  // segment length and number of segments of a row
 };
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
@@ -124,17 +193,18 @@ __device__ __forceinline__ float dt_weight(int ga, int gb, float inv_sigma_s, fl
 
 // Stage the packed window columns and the per-position window statistics of
 // both images for row y and disparity chunk d0 (reads the 2R+1 image rows once).
-template <int R>
+template <int R, int LPS>
 __device__ void stage_zncc(const HArgs& a, const HLayout& lay, uint32_t* smem, int y, int d0, int mode) {
   constexpr int NP = packs_of(R);
   constexpr int N = (2 * R + 1) * (2 * R + 1);
+  constexpr int P = LPS - 1;
   const int tid = threadIdx.x, nt = blockDim.x, W = a.W, H = a.H;
   uint32_t* LP = smem + lay.oLP;
   uint32_t* TP = smem + lay.oTP;
   int rows_off[NP * 4];
 #pragma unroll
   for (int q = 0; q < NP * 4; ++q) rows_off[q] = (q < 2 * R + 1) ? clampi(y - R + q, 0, H - 1) * a.pitch : -1;
-  for (int i = tid; i < lay.nLP; i += nt) {
+  for (int i = tid; i < W + 2 * R; i += nt) {
     const int col = clampi(i - R, 0, W - 1);
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
@@ -145,8 +215,8 @@ __device__ void stage_zncc(const HArgs& a, const HLayout& lay, uint32_t* smem, i
       LP[k * lay.nLP + i] = p;
     }
   }
-  for (int i = tid; i < lay.nTP; i += nt) {
-    const int col = clampi(i - 63 - R - d0, 0, W - 1);
+  for (int i = tid; i < lay.nTS + 2 * R; i += nt) {
+    const int col = clampi(i - P - R - d0, 0, W - 1);
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
       uint32_t p = 0;
@@ -180,8 +250,8 @@ __device__ void stage_zncc(const HArgs& a, const HLayout& lay, uint32_t* smem, i
       if (a.s_ll) a.s_ll[(size_t)y * W + x] = (int)ss;
     }
   }
-  // target statistics at x' = t - 63 - d0: columns x'-R..x'+R are TP entries t .. t+2R
-  for (int t = tid; t < W + 63; t += nt) {
+  // target statistics at x' = t - P - d0: columns x'-R..x'+R are TP entries t .. t+2R
+  for (int t = tid; t < lay.nTS; t += nt) {
     uint32_t s = 0, ss = 0;
 #pragma unroll
     for (int i = 0; i <= 2 * R; ++i)
@@ -196,8 +266,8 @@ __device__ void stage_zncc(const HArgs& a, const HLayout& lay, uint32_t* smem, i
     TI[t] = v > 0 ? 1.0f / sqrtf((float)v) : 0.0f;
     if (mode == kSums) {
       // each x' in [-(D-1), W-1] is written by exactly one chunk
-      const int xe = t - 63 - d0;
-      const bool own = (blockIdx.x == 0) ? (xe >= -63) : (xe <= -d0);
+      const int xe = t - P - d0;
+      const bool own = (blockIdx.x == 0) ? (xe >= -P) : (xe <= -d0);
       if (own && xe >= -(a.D - 1) && xe <= W - 1) {
         const size_t idx = (size_t)y * (W + a.D - 1) + xe + a.D - 1;
         if (a.s_t) a.s_t[idx] = (int)s;
@@ -215,13 +285,14 @@ __device__ void stage_row_weights(const HArgs& a, float* WH, int y) {
 }
 
 // Cross-sum column at column p for this lane's disparity: sum_k dot4(L pack, T pack).
-template <int R>
+template <int R, int LPS>
 __device__ __forceinline__ uint32_t colsum(const uint32_t* LP, const uint32_t* TP, int nLP, int nTP, int p,
-                                           int lane) {
+                                           int dloc) {
   constexpr int NP = packs_of(R);
   uint32_t s = 0;
 #pragma unroll
-  for (int k = 0; k < NP; ++k) s = __builtin_amdgcn_udot4(LP[k * nLP + p + R], TP[k * nTP + p + R + 63 - lane], s, false);
+  for (int k = 0; k < NP; ++k)
+    s = __builtin_amdgcn_udot4(LP[k * nLP + p + R], TP[k * nTP + p + R + LPS - 1 - dloc], s, false);
   return s;
 }
 
@@ -241,7 +312,6 @@ __device__ __forceinline__ float zncc_cost_from(uint32_t srt, int sl, float il, 
 // ranges from ~1 at edges to 1/(1-K) per pass in flat areas, pushes values out
 // of FP16's range.  BF16 and FP32 volumes store plain values.
 // ---------------------------------------------------------------------------
-constexpr int kExpBias = 14;
 
 // Maximum of a non-negative 32-bit key over the 64 lanes (result from lane 63).
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
@@ -260,35 +330,43 @@ __device__ __forceinline__ int wave_exponent(float v) {
   return m ? (int)(m >> 23) - 127 : 0;
 }
 
-template <typename T>
-__device__ __forceinline__ float load_scaled(const T* p, float scale) {
-  return Elem<T>::load(p) * scale;
-}
-
-template <int R, int SEG, typename T, int MODE>
+template <int R, int SEG, int LPS, typename T, int MODE>
 __global__ __launch_bounds__(1024) void hpass_kernel(HArgs a) {
   extern __shared__ uint32_t smem[];
   constexpr int NW = 2 * R + 1;  // window side
   constexpr int N = NW * NW;
+  constexpr int SPW = kWave / LPS;  // segments per wave
   constexpr bool kZncc = MODE != kHPair;
   constexpr bool kDT = MODE == kCostHPair || MODE == kHPair;
   constexpr bool kHalf = std::is_same<T, _Float16>::value;
-  const int y = blockIdx.y, d0 = blockIdx.x * kWave;
+  static_assert(LPS == 64 || LPS == 32, "lanes per segment");
+  static_assert(!(kHalf && LPS != 64), "FP16 exponents are per 64-lane wave");
+  constexpr uint32_t kBytes = sizeof(T);
+  const int y = blockIdx.y, d0 = blockIdx.x * LPS;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int d = d0 + lane;
+  const int dloc = lane & (LPS - 1);
+  const int seg = wave * SPW + (SPW == 1 ? 0 : lane / LPS);
+  const int d = d0 + dloc;
   const bool active = d < a.D;
-  const int dl = active ? d : a.D - 1;  // loads of idle lanes read a valid element
-  const int W = a.W;
-  const HLayout lay = h_layout(W, R, kZncc, kDT);
-  if constexpr (kZncc) stage_zncc<R>(a, lay, smem, y, d0, MODE);
+  const int W = a.W, D = a.D;
+  // Two segments per wave are only used when the row splits into full segments
+  // of exactly SEG values (checked by the host), so every step is in the row.
+  constexpr bool kFull = LPS == 32;
+  const HLayout lay = h_layout(W, R, LPS, SEG, kZncc, kDT);
+  if constexpr (kZncc) stage_zncc<R, LPS>(a, lay, smem, y, d0, MODE);
   if constexpr (kDT) stage_row_weights(a, (float*)(smem + lay.oWH), y);
   __syncthreads();
 
-  const int x0 = wave * a.segl;
-  const int len = min(a.segl, W - x0);  // >= 1, wave-uniform
-  const size_t rowbase = (size_t)y * W * a.D;
-  T* vol = (T*)a.vol;
+  // segment [x0, x0 + len)
+  const int x0 = seg * a.segl;
+  const int len = kFull ? SEG : min(a.segl, W - x0);
+  const uint32_t rowbytes = (uint32_t)W * D * kBytes;
+  const uint32_t xstride = (uint32_t)D * kBytes;
+  const rsrc_t vrs = make_rsrc((const char*)a.vol + (size_t)y * rowbytes, rowbytes);
+  const uint32_t voff = ((uint32_t)x0 * D + (uint32_t)(active ? d : D - 1)) * kBytes;
+  // uniform offset of step k, clamped into the segment
+  auto step_soff = [&](int k) -> uint32_t { return (uint32_t)(kFull ? k : min(k, len - 1)) * xstride; };
 
   const uint32_t* LP = smem + lay.oLP;
   const uint32_t* TP = smem + lay.oTP;
@@ -298,13 +376,16 @@ __global__ __launch_bounds__(1024) void hpass_kernel(HArgs a) {
   const float* TI = (const float*)(smem + lay.oTI);
 
   if constexpr (MODE == kSums || MODE == kCost) {
+    static_assert(LPS == 64, "streaming modes use one segment per wave");
     if (MODE == kSums && a.s_rt == nullptr) return;
+    T* vol = (T*)a.vol;
+    const size_t rowbase = (size_t)y * W * D;
     // running window: ring[s] holds the column sums of columns x0-R+s (mod NW)
     uint32_t ring[NW];
     uint32_t S = 0;
 #pragma unroll
     for (int i = 0; i < NW; ++i) {
-      ring[i] = colsum<R>(LP, TP, lay.nLP, lay.nTP, x0 - R + i, lane);
+      ring[i] = colsum<R, LPS>(LP, TP, lay.nLP, lay.nTP, x0 - R + i, dloc);
       S += ring[i];
     }
     for (int kb = 0; kb < len; kb += NW) {
@@ -315,16 +396,16 @@ __global__ __launch_bounds__(1024) void hpass_kernel(HArgs a) {
           const int x = x0 + k;
           if (k > 0) {
             const int slot = (u + NW - 1) % NW;
-            const uint32_t cn = colsum<R>(LP, TP, lay.nLP, lay.nTP, x + R, lane);
+            const uint32_t cn = colsum<R, LPS>(LP, TP, lay.nLP, lay.nTP, x + R, dloc);
             S = S + cn - ring[slot];
             ring[slot] = cn;
           }
           if (active) {
-            const size_t idx = rowbase + (size_t)x * a.D + d;
+            const size_t idx = rowbase + (size_t)x * D + d;
             if constexpr (MODE == kSums) {
               a.s_rt[idx] = (int32_t)S;
             } else {
-              const float c = zncc_cost_from(S, LS[x], LI[x], TS[x + 63 - lane], TI[x + 63 - lane], N);
+              const float c = zncc_cost_from(S, LS[x], LI[x], TS[x + LPS - 1 - dloc], TI[x + LPS - 1 - dloc], N);
               Elem<T>::store(vol + idx, c * a.out_scale);
             }
           }
@@ -339,8 +420,9 @@ __global__ __launch_bounds__(1024) void hpass_kernel(HArgs a) {
     float* EX2 = (float*)(smem + lay.oEX2);
     float* EXS2 = (float*)(smem + lay.oEXS2);
     const bool scaled = kHalf && a.ex != nullptr;
-    const int nck = (a.D + kWave - 1) / kWave;
+    const int nck = (D + kWave - 1) / kWave;
     int8_t* exrow = scaled ? a.ex + (size_t)y * W * nck + blockIdx.x : nullptr;
+    const float* wp = WH + x0;  // W_L at x0 + k; padded past the row
     float c[SEG];
     // ---- loop A: values of the segment + carry-free L pass (ell) and weight product P
     float ell = 0.0f, P = 1.0f;
@@ -349,90 +431,94 @@ __global__ __launch_bounds__(1024) void hpass_kernel(HArgs a) {
       uint32_t S = 0;
 #pragma unroll
       for (int i = 0; i < NW; ++i) {
-        ring[i] = colsum<R>(LP, TP, lay.nLP, lay.nTP, x0 - R + i, lane);
+        ring[i] = colsum<R, LPS>(LP, TP, lay.nLP, lay.nTP, x0 - R + i, dloc);
         S += ring[i];
       }
 #pragma unroll
       for (int k = 0; k < SEG; ++k) {
         const bool in = k < len;
-        const int x = x0 + (in ? k : len - 1);
+        const int x = x0 + k;
         if (k > 0) {
           const int slot = (k - 1) % NW;
-          const uint32_t cn = colsum<R>(LP, TP, lay.nLP, lay.nTP, x + R, lane);
+          const uint32_t cn = colsum<R, LPS>(LP, TP, lay.nLP, lay.nTP, x + R, dloc);
           S = S + cn - ring[slot];
           ring[slot] = cn;
         }
-        c[k] = zncc_cost_from(S, LS[x], LI[x], TS[x + 63 - lane], TI[x + 63 - lane], N);
-        const float w = WH[x];
+        c[k] = zncc_cost_from(S, LS[x], LI[x], TS[x + LPS - 1 - dloc], TI[x + LPS - 1 - dloc], N);
+        const float w = wp[k];
         ell = in ? fmaf(w, ell, c[k]) : ell;
         P = in ? P * w : P;
+        if (k % 2 == 1) {
+          pin(ell, P, S);
+          fence();
+        }
       }
     } else {
-      const T* src = vol + rowbase + (size_t)x0 * a.D + dl;
 #pragma unroll
-      for (int k = 0; k < SEG; ++k) {
-        const int kk = k < len ? k : len - 1;
-        c[k] = Elem<T>::load(src + (size_t)kk * a.D);
-      }
+      for (int k = 0; k < SEG; ++k) c[k] = Elem<T>::bload(vrs, voff, step_soff(k));
+      __builtin_amdgcn_sched_barrier(0);
       if (scaled) {
 #pragma unroll
-        for (int k = 0; k < SEG; ++k) {
-          const int kk = k < len ? k : len - 1;
-          c[k] = ldexpf(c[k], (int)exrow[(size_t)(x0 + kk) * nck] - kExpBias);
-        }
+        for (int k = 0; k < SEG; ++k)
+          c[k] = ldexpf(c[k], (int)exrow[(size_t)(x0 + min(k, len - 1)) * nck] - kExpBias);
       }
 #pragma unroll
       for (int k = 0; k < SEG; ++k) {
         const bool in = k < len;
-        const float w = WH[x0 + (in ? k : len - 1)];
+        const float w = wp[k];
         ell = in ? fmaf(w, ell, c[k]) : ell;
         P = in ? P * w : P;
+        step_fence(k, ell, P);
       }
     }
-    EX[wave * kWave + lane] = ell;
-    if (lane == 0) EXS[wave] = P;
+    // every lane stores its segment's weight product (one value per segment):
+    // a single-lane store lets the compiler defer the product chain and keep
+    // the whole line of weights live until then
+    EX[seg * LPS + dloc] = ell;
+    EXS[seg] = P;
     __syncthreads();
     float carry = 0.0f;
-    for (int s = 0; s < wave; ++s) carry = fmaf(EXS[s], carry, EX[s * kWave + lane]);
+    for (int s = 0; s < seg; ++s) carry = fmaf(EXS[s], carry, EX[s * LPS + dloc]);
+    reload_fence();
     // ---- loop B: exact L pass from the true carry; accumulate the carry-free R value at x0
     float prev = carry, acc = 0.0f, pi = 1.0f;
 #pragma unroll
     for (int k = 0; k < SEG; ++k) {
       const bool in = k < len;
-      const float w = WH[x0 + (in ? k : len - 1)];
+      const float w = wp[k];
       const float cl = fmaf(w, prev, c[k]);
       c[k] = in ? cl : c[k];
       prev = in ? cl : prev;
       if (k > 0) pi = in ? pi * w : pi;
       acc = in ? fmaf(cl, pi, acc) : acc;
+      step_fence(k, prev, acc, pi);
     }
     const float Q = pi * WH[x0 + len];
-    EX2[wave * kWave + lane] = acc;
-    if (lane == 0) EXS2[wave] = Q;
+    EX2[seg * LPS + dloc] = acc;
+    EXS2[seg] = Q;
     __syncthreads();
     float kappa = 0.0f;
-    for (int s = a.nw - 1; s > wave; --s) kappa = fmaf(EXS2[s], kappa, EX2[s * kWave + lane]);
+    for (int s = a.nseg - 1; s > seg; --s) kappa = fmaf(EXS2[s], kappa, EX2[s * LPS + dloc]);
+    reload_fence();
     // ---- loop D: exact R pass from the true carry, then store
     float next = kappa;
 #pragma unroll
     for (int k = SEG - 1; k >= 0; --k) {
       const bool in = k < len;
-      const float cr = fmaf(WH[x0 + (in ? k + 1 : len)], next, c[k]);
+      const float cr = fmaf(wp[k + 1], next, c[k]);
       c[k] = in ? cr : c[k];
       next = in ? cr : next;
+      step_fence(SEG - 1 - k, next);
     }
-    T* dst = vol + rowbase + (size_t)x0 * a.D + d;
 #pragma unroll
     for (int k = 0; k < SEG; ++k) {
-      if (k < len) {
-        float v = c[k] * a.out_scale;
-        if (scaled) {
-          const int e = wave_exponent(active ? v : 0.0f);
-          v = ldexpf(v, kExpBias - e);
-          if (lane == 0) exrow[(size_t)(x0 + k) * nck] = (int8_t)e;
-        }
-        if (active) Elem<T>::store(dst + (size_t)k * a.D, v);
+      float v = c[k] * a.out_scale;
+      if (scaled && k < len) {
+        const int e = wave_exponent(active ? v : 0.0f);
+        v = ldexpf(v, kExpBias - e);
+        if (lane == 0) exrow[(size_t)(x0 + k) * nck] = (int8_t)e;
       }
+      if (k < len && active) Elem<T>::bstore(vrs, voff, step_soff(k), v);
     }
   }
 }
@@ -452,7 +538,10 @@ struct VArgs {
   int segl, nw;
 };
 
-__host__ __device__ inline int v_lds_words(int H, int DPL) { return (H + 1) + 2 * (kMaxWaves * kWave * DPL + kMaxWaves); }
+// WV[H+1] (+ SEG spare entries), EX/EX2 [16*64*DPL], EXS/EXS2 [16]
+__host__ __device__ inline int v_lds_words(int H, int SEG, int DPL) {
+  return (H + 1 + SEG) + 2 * (kMaxWaves * kWave * DPL + kMaxWaves);
+}
 
 __device__ __forceinline__ float wave_min(float v) {
 #pragma unroll
@@ -464,13 +553,14 @@ template <int SEG, typename T, int DPL, bool WTA>
 __global__ __launch_bounds__(1024) void vpass_kernel(VArgs a) {
   extern __shared__ uint32_t smem[];
   constexpr bool kHalf = std::is_same<T, _Float16>::value;
+  constexpr uint32_t kBytes = sizeof(T);
   const int chunk = blockIdx.x, x = blockIdx.y;
   const int d0 = chunk * kWave * DPL;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int W = a.W, H = a.H, D = a.D;
   float* WV = (float*)smem;
-  float* EX = WV + (H + 1);
+  float* EX = WV + (H + 1 + SEG);
   float* EXS = EX + kMaxWaves * kWave * DPL;
   float* EX2 = EXS + kMaxWaves;
   float* EXS2 = EX2 + kMaxWaves * kWave * DPL;
@@ -481,38 +571,36 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs a) {
   __syncthreads();
   const int y0 = wave * a.segl;
   const int len = min(a.segl, H - y0);  // >= 1, wave-uniform
-  const size_t rowstride = (size_t)W * D;
-  T* vol = (T*)a.vol;
+  const uint32_t rowbytes = (uint32_t)W * D * kBytes;
+  // buffer over the volume from column x on; every offset below stays inside it
+  const rsrc_t vrs = make_rsrc((const char*)a.vol + (size_t)x * D * kBytes,
+                               (uint32_t)((size_t)H * W * D * kBytes - (size_t)x * D * kBytes));
   const bool scaled = kHalf && a.ex != nullptr;
   const int nck = (D + kWave - 1) / kWave;
+  auto yat = [&](int k) -> int { return y0 + (k < len ? k : len - 1); };
+  const float* wp = WV + y0;  // W_U at y0 + k; padded past the column
   bool act[DPL];
-  int dl[DPL];
+  uint32_t voff[DPL];
 #pragma unroll
   for (int j = 0; j < DPL; ++j) {
-    act[j] = d0 + lane + kWave * j < D;
-    dl[j] = act[j] ? d0 + lane + kWave * j : D - 1;
+    const int dj = d0 + lane + kWave * j;
+    act[j] = dj < D;
+    voff[j] = (uint32_t)(act[j] ? dj : D - 1) * kBytes;
   }
 
   float c[DPL][SEG];
 #pragma unroll
-  for (int j = 0; j < DPL; ++j) {
-    const T* src = vol + (size_t)y0 * rowstride + (size_t)x * D + dl[j];
+  for (int k = 0; k < SEG; ++k)
 #pragma unroll
-    for (int k = 0; k < SEG; ++k) {
-      const int kk = k < len ? k : len - 1;
-      c[j][k] = Elem<T>::load(src + (size_t)kk * rowstride);
-    }
-  }
+    for (int j = 0; j < DPL; ++j) c[j][k] = Elem<T>::bload(vrs, voff[j], (uint32_t)yat(k) * rowbytes);
+  __builtin_amdgcn_sched_barrier(0);
   if (scaled) {
 #pragma unroll
     for (int j = 0; j < DPL; ++j) {
       if (chunk * DPL + j >= nck) continue;  // no disparity of this lane group exists
-      const int8_t* ex = a.ex + (size_t)y0 * W * nck + (size_t)x * nck + chunk * DPL + j;
+      const int8_t* ex = a.ex + (size_t)x * nck + chunk * DPL + j;
 #pragma unroll
-      for (int k = 0; k < SEG; ++k) {
-        const int kk = k < len ? k : len - 1;
-        c[j][k] = ldexpf(c[j][k], (int)ex[(size_t)kk * W * nck] - kExpBias);
-      }
+      for (int k = 0; k < SEG; ++k) c[j][k] = ldexpf(c[j][k], (int)ex[(size_t)yat(k) * W * nck] - kExpBias);
     }
   }
   // ---- loop A: carry-free U pass
@@ -522,14 +610,20 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs a) {
 #pragma unroll
   for (int k = 0; k < SEG; ++k) {
     const bool in = k < len;
-    const float w = WV[y0 + (in ? k : len - 1)];
+    const float w = wp[k];
 #pragma unroll
     for (int j = 0; j < DPL; ++j) ell[j] = in ? fmaf(w, ell[j], c[j][k]) : ell[j];
     P = in ? P * w : P;
+    if (k % kBlock == kBlock - 1) {
+#pragma unroll
+      for (int j = 0; j < DPL; ++j) pin(ell[j]);
+      pin(P);
+      fence();
+    }
   }
 #pragma unroll
   for (int j = 0; j < DPL; ++j) EX[(wave * DPL + j) * kWave + lane] = ell[j];
-  if (lane == 0) EXS[wave] = P;
+  EXS[wave] = P;  // from every lane (see the H pass)
   __syncthreads();
   float prev[DPL];
 #pragma unroll
@@ -538,6 +632,7 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs a) {
     for (int s = 0; s < wave; ++s) carry = fmaf(EXS[s], carry, EX[(s * DPL + j) * kWave + lane]);
     prev[j] = carry;
   }
+  reload_fence();
   // ---- loop B: exact U pass; carry-free D value at y0
   float acc[DPL], pi = 1.0f;
 #pragma unroll
@@ -545,7 +640,7 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs a) {
 #pragma unroll
   for (int k = 0; k < SEG; ++k) {
     const bool in = k < len;
-    const float w = WV[y0 + (in ? k : len - 1)];
+    const float w = wp[k];
     if (k > 0) pi = in ? pi * w : pi;
 #pragma unroll
     for (int j = 0; j < DPL; ++j) {
@@ -554,11 +649,17 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs a) {
       prev[j] = in ? cu : prev[j];
       acc[j] = in ? fmaf(cu, pi, acc[j]) : acc[j];
     }
+    if (k % kBlock == kBlock - 1) {
+#pragma unroll
+      for (int j = 0; j < DPL; ++j) pin(prev[j], acc[j]);
+      pin(pi);
+      fence();
+    }
   }
   const float Q = pi * WV[y0 + len];
 #pragma unroll
   for (int j = 0; j < DPL; ++j) EX2[(wave * DPL + j) * kWave + lane] = acc[j];
-  if (lane == 0) EXS2[wave] = Q;
+  EXS2[wave] = Q;
   __syncthreads();
   float next[DPL];
 #pragma unroll
@@ -567,23 +668,28 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs a) {
     for (int s = a.nw - 1; s > wave; --s) kappa = fmaf(EXS2[s], kappa, EX2[(s * DPL + j) * kWave + lane]);
     next[j] = kappa;
   }
+  reload_fence();
   // ---- loop D: exact D pass
 #pragma unroll
   for (int k = SEG - 1; k >= 0; --k) {
     const bool in = k < len;
-    const float w = WV[y0 + (in ? k + 1 : len)];
+    const float w = wp[k + 1];
 #pragma unroll
     for (int j = 0; j < DPL; ++j) {
       const float cd = fmaf(w, next[j], c[j][k]);
       c[j][k] = in ? cd : c[j][k];
       next[j] = in ? cd : next[j];
     }
+    if ((SEG - 1 - k) % kBlock == kBlock - 1) {
+#pragma unroll
+      for (int j = 0; j < DPL; ++j) pin(next[j]);
+      fence();
+    }
   }
   if constexpr (!WTA) {
 #pragma unroll
     for (int j = 0; j < DPL; ++j) {
-      T* dst = vol + (size_t)y0 * rowstride + (size_t)x * D + d0 + lane + kWave * j;
-      int8_t* ex = scaled ? a.ex + (size_t)y0 * W * nck + (size_t)x * nck + chunk * DPL + j : nullptr;
+      int8_t* ex = scaled ? a.ex + (size_t)x * nck + chunk * DPL + j : nullptr;
 #pragma unroll
       for (int k = 0; k < SEG; ++k)
         if (k < len) {
@@ -591,9 +697,9 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs a) {
           if (scaled) {
             const int e = wave_exponent(act[j] ? v : 0.0f);
             v = ldexpf(v, kExpBias - e);
-            if (lane == 0) ex[(size_t)k * W * nck] = (int8_t)e;
+            if (lane == 0) ex[(size_t)(y0 + k) * W * nck] = (int8_t)e;
           }
-          if (act[j]) Elem<T>::store(dst + (size_t)k * rowstride, v);
+          if (act[j]) Elem<T>::bstore(vrs, voff[j], (uint32_t)(y0 + k) * rowbytes, v);
         }
     }
   } else {

@@ -34,14 +34,27 @@ int launch(const char* name, Kernel kernel, dim3 grid, dim3 block, size_t lds, h
   return ZDT_OK;
 }
 
-// Segment lengths (values per lane) compiled for the H and V passes.
-constexpr int kHSegs[] = {20, 40, 80};
+// Segment lengths (values per lane) compiled for the H and V passes.  H
+// passes over FP32 volumes give each wave two segments of 32 disparities (a
+// 128-byte line per half-wave); 16-bit volumes one segment of 64 disparities.
+constexpr int kHSegs32[] = {8, 20, 40};    // LPS = 32: up to 32 segments per row
+constexpr int kHSegs64[] = {16, 40, 80};   // LPS = 64: up to 16 segments per row
 constexpr int kVSegs[] = {8, 12, 24, 48, 72};
 constexpr int kNumHSegs = 3, kNumVSegs = 5;
+// FP32 H pairs take two segments per wave when the row splits into an even
+// number (<= 32) of full segments of a compiled length; otherwise one.
+inline int h_full_seg32(int W) {
+  for (int seg : kHSegs32)
+    if (W % seg == 0 && (W / seg) % 2 == 0 && W / seg <= 2 * kMaxWaves) return seg;
+  return 0;
+}
+inline int h_lps(int dtype, int mode, int W) {
+  return (dtype == ZDT_F32 && (mode == kCostHPair || mode == kHPair) && h_full_seg32(W)) ? 32 : 64;
+}
 
 // Kernel dispatch, one set per volume element type (defined in zdt_inst_*.hip).
 #define ZDT_DECLARE_DISPATCH(SUFFIX)                                                                      \
-  int dispatch_h_##SUFFIX(int mode, int R, int seg, const HArgs& a, hipStream_t s);                     \
+  int dispatch_h_##SUFFIX(int mode, int R, int seg, int lps, const HArgs& a, hipStream_t s);            \
   int dispatch_v_##SUFFIX(int seg, int dpl, bool wta, const VArgs& a, int nchunks, hipStream_t s);     \
   int dispatch_wta_##SUFFIX(const void* vol, int npix, int D, int32_t* disp, hipStream_t s);
 ZDT_DECLARE_DISPATCH(f32)

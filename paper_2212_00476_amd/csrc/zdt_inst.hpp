@@ -8,33 +8,43 @@
 namespace zdt {
 namespace inst {
 
-template <int R, int SEG, typename T, int MODE>
+template <int R, int SEG, int LPS, typename T, int MODE>
 int run_h(const HArgs& a, hipStream_t s) {
-  const HLayout lay = h_layout(a.W, R, MODE != kHPair, MODE == kCostHPair || MODE == kHPair);
+  const HLayout lay = h_layout(a.W, R, LPS, SEG, MODE != kHPair, MODE == kCostHPair || MODE == kHPair);
   static const char* const names[] = {"zncc_sums", "zncc_cost", "zncc_hpair", "dt_hpair"};
-  return launch(names[MODE], hpass_kernel<R, SEG, T, MODE>, dim3((a.D + kWave - 1) / kWave, a.H),
-                dim3(kWave * a.nw), (size_t)lay.words * 4, s, a);
+  const int spw = kWave / LPS;
+  const int nw = (a.nseg + spw - 1) / spw;
+  return launch(names[MODE], hpass_kernel<R, SEG, LPS, T, MODE>, dim3((a.D + LPS - 1) / LPS, a.H), dim3(kWave * nw),
+                (size_t)lay.words * 4, s, a);
 }
 
-template <int R, typename T, int MODE>
+template <int R, int LPS, typename T, int MODE>
 int run_h_seg(int seg, const HArgs& a, hipStream_t s) {
-  switch (seg) {
-    case 20: return run_h<R, 20, T, MODE>(a, s);
-    case 40: return run_h<R, 40, T, MODE>(a, s);
-    case 80: return run_h<R, 80, T, MODE>(a, s);
+  if constexpr (LPS == 32) {
+    switch (seg) {
+      case 8: return run_h<R, 8, LPS, T, MODE>(a, s);
+      case 20: return run_h<R, 20, LPS, T, MODE>(a, s);
+      case 40: return run_h<R, 40, LPS, T, MODE>(a, s);
+    }
+  } else {
+    switch (seg) {
+      case 16: return run_h<R, 16, LPS, T, MODE>(a, s);
+      case 40: return run_h<R, 40, LPS, T, MODE>(a, s);
+      case 80: return run_h<R, 80, LPS, T, MODE>(a, s);
+    }
   }
   return fail(ZDT_EUNSUPPORTED, "no H-pass instance for segment length %d", seg);
 }
 
 // Streaming modes (sums, raw cost) keep no per-segment registers: SEG = 0.
-template <typename T, int MODE>
+template <typename T, int MODE, int LPS>
 int run_h_radius(int R, int seg, const HArgs& a, hipStream_t s) {
   constexpr bool stream = MODE == kSums || MODE == kCost;
   switch (R) {
-#define ZDT_CASE(RR)                               \
-  case RR:                                         \
-    if constexpr (stream) return run_h<RR, 0, T, MODE>(a, s); \
-    else return run_h_seg<RR, T, MODE>(seg, a, s);
+#define ZDT_CASE(RR)                                                \
+  case RR:                                                          \
+    if constexpr (stream) return run_h<RR, 0, 64, T, MODE>(a, s);   \
+    else return run_h_seg<RR, LPS, T, MODE>(seg, a, s);
     ZDT_CASE(0) ZDT_CASE(1) ZDT_CASE(2) ZDT_CASE(3) ZDT_CASE(4) ZDT_CASE(5) ZDT_CASE(6)
 #undef ZDT_CASE
   }
@@ -44,7 +54,7 @@ int run_h_radius(int R, int seg, const HArgs& a, hipStream_t s) {
 template <int SEG, typename T, int DPL, bool WTA>
 int run_v(const VArgs& a, int nchunks, hipStream_t s) {
   return launch(WTA ? "dt_vpair_wta" : "dt_vpair", vpass_kernel<SEG, T, DPL, WTA>, dim3(nchunks, a.W),
-                dim3(kWave * a.nw), (size_t)v_lds_words(a.H, DPL) * 4, s, a);
+                dim3(kWave * a.nw), (size_t)v_lds_words(a.H, SEG, DPL) * 4, s, a);
 }
 
 template <typename T, int DPL, bool WTA>
@@ -67,23 +77,41 @@ int run_v_seg(int seg, const VArgs& a, int nchunks, hipStream_t s) {
 
 namespace zdt {
 
-int ZDT_CAT(dispatch_h_, ZDT_SUFFIX)(int mode, int R, int seg, const HArgs& a, hipStream_t s) {
+int ZDT_CAT(dispatch_h_, ZDT_SUFFIX)(int mode, int R, int seg, int lps, const HArgs& a, hipStream_t s) {
   using T = ZDT_ELEM;
+  constexpr bool f32 = std::is_same<T, float>::value;
   switch (mode) {
-    case kCost: return inst::run_h_radius<T, kCost>(R, seg, a, s);
-    case kCostHPair: return inst::run_h_radius<T, kCostHPair>(R, seg, a, s);
-    case kHPair: return inst::run_h_seg<0, T, kHPair>(seg, a, s);
+    case kCost: return inst::run_h_radius<T, kCost, 64>(R, seg, a, s);
+    case kCostHPair:
+      if constexpr (f32) {
+        if (lps == 32) return inst::run_h_radius<T, kCostHPair, 32>(R, seg, a, s);
+      }
+      if (lps == 64) return inst::run_h_radius<T, kCostHPair, 64>(R, seg, a, s);
+      break;
+    case kHPair:
+      if constexpr (f32) {
+        if (lps == 32) return inst::run_h_seg<0, 32, T, kHPair>(seg, a, s);
+      }
+      if (lps == 64) return inst::run_h_seg<0, 64, T, kHPair>(seg, a, s);
+      break;
     case kSums:
-      if constexpr (std::is_same<T, float>::value) return inst::run_h_radius<T, kSums>(R, seg, a, s);
+      if constexpr (f32) return inst::run_h_radius<T, kSums, 64>(R, seg, a, s);
       break;
   }
-  return fail(ZDT_EUNSUPPORTED, "no H-pass instance for mode %d", mode);
+  return fail(ZDT_EUNSUPPORTED, "no H-pass instance for mode %d, %d lanes per segment", mode, lps);
 }
 
 int ZDT_CAT(dispatch_v_, ZDT_SUFFIX)(int seg, int dpl, bool wta, const VArgs& a, int nchunks, hipStream_t s) {
   using T = ZDT_ELEM;
   if (!wta) return inst::run_v_seg<T, 1, false>(seg, a, nchunks, s);
-  if (dpl == 2) return inst::run_v_seg<T, 2, true>(seg, a, nchunks, s);
+  if (dpl == 2) {
+    switch (seg) {
+      case 8: return inst::run_v<8, T, 2, true>(a, nchunks, s);
+      case 12: return inst::run_v<12, T, 2, true>(a, nchunks, s);
+      case 24: return inst::run_v<24, T, 2, true>(a, nchunks, s);
+    }
+    return fail(ZDT_EUNSUPPORTED, "no two-disparity-per-lane V instance for segment length %d", seg);
+  }
   return inst::run_v_seg<T, 1, true>(seg, a, nchunks, s);
 }
 

@@ -88,30 +88,39 @@ int check_params(const zdt_params* p, const char* who) {
     if (r != 0) return fail(ZDT_EINVAL, "%s: reserved fields must be zero", who);
   const long long nvol = (long long)p->width * p->height * p->max_disp;
   if (nvol >= (1LL << 31)) return fail(ZDT_EUNSUPPORTED, "%s: W*H*D = %lld exceeds 2^31-1 elements", who, nvol);
-  if (p->width > kMaxWaves * kHSegs[kNumHSegs - 1])
-    return fail(ZDT_EUNSUPPORTED, "%s: width %d > %d", who, p->width, kMaxWaves * kHSegs[kNumHSegs - 1]);
+  if ((long long)nvol * (long long)dtype_size(p->vol_dtype) >= (1LL << 32))
+    return fail(ZDT_EUNSUPPORTED, "%s: the volume must stay below 4 GiB (32-bit buffer offsets)", who);
+  if (p->width > kMaxWaves * kHSegs64[kNumHSegs - 1])
+    return fail(ZDT_EUNSUPPORTED, "%s: width %d > %d", who, p->width, kMaxWaves * kHSegs64[kNumHSegs - 1]);
   if (p->height > kMaxWaves * kVSegs[kNumVSegs - 1])
     return fail(ZDT_EUNSUPPORTED, "%s: height %d > %d", who, p->height, kMaxWaves * kVSegs[kNumVSegs - 1]);
   return ZDT_OK;
 }
 
-// A line of n values split into nw <= 16 wave segments of segl <= seg values.
+// A line of n values split into nseg <= maxseg segments of segl <= seg values
+// (the smallest compiled seg that fits).
 struct Split {
-  int seg, segl, nw;
+  int seg, segl, nseg;
 };
 
-Split split_line(int n, const int* segs, int nsegs) {
+Split split_line(int n, const int* segs, int nsegs, int maxseg) {
   for (int i = 0; i < nsegs; ++i)
-    if (n <= kMaxWaves * segs[i]) {
-      const int nw0 = (n + segs[i] - 1) / segs[i];
-      const int segl = (n + nw0 - 1) / nw0;
+    if (n <= maxseg * segs[i]) {
+      const int n0 = (n + segs[i] - 1) / segs[i];
+      const int segl = (n + n0 - 1) / n0;
       return {segs[i], segl, (n + segl - 1) / segl};
     }
   return {0, 0, 0};
 }
 
-Split h_split(const zdt_params* p) { return split_line(p->width, kHSegs, kNumHSegs); }
-Split v_split(const zdt_params* p) { return split_line(p->height, kVSegs, kNumVSegs); }
+Split h_split(const zdt_params* p, int lps) {
+  if (lps == 32) {
+    const int seg = h_full_seg32(p->width);
+    return {seg, seg, p->width / seg};
+  }
+  return split_line(p->width, kHSegs64, kNumHSegs, kMaxWaves);
+}
+Split v_split(const zdt_params* p) { return split_line(p->height, kVSegs, kNumVSegs, kMaxWaves); }
 
 bool normalized(const zdt_params* p) { return (p->flags & ZDT_FLAG_NORMALIZE) || p->vol_dtype != ZDT_F32; }
 
@@ -146,7 +155,7 @@ HArgs make_hargs(const zdt_params* p, const uint8_t* left, const uint8_t* right,
   a.out_scale = out_scale;
   a.vol = vol;
   a.segl = sp.segl;
-  a.nw = sp.nw;
+  a.nseg = sp.nseg;
   return a;
 }
 
@@ -162,15 +171,29 @@ VArgs make_vargs(const zdt_params* p, const uint8_t* guide, void* vol, float out
   a.out_scale = out_scale;
   a.vol = vol;
   a.segl = sp.segl;
-  a.nw = sp.nw;
+  a.nw = sp.nseg;
   return a;
 }
 
-int dispatch_h(int dtype, int mode, int R, int seg, const HArgs& a, hipStream_t s) {
+// Launch an H-pass mode: the lane layout follows the volume type and mode.
+int run_h_mode(const zdt_params* p, int dtype, int mode, const uint8_t* left, const uint8_t* right,
+               const uint8_t* guide, void* vol, float scale, int8_t* ex, hipStream_t s, HArgs* extra = nullptr) {
+  const int lps = h_lps(dtype, mode, p->width);
+  const Split sp = h_split(p, lps);
+  HArgs a = make_hargs(p, left, right, guide, vol, scale, sp);
+  a.ex = ex;
+  if (extra) {
+    a.s_rt = extra->s_rt;
+    a.s_l = extra->s_l;
+    a.s_ll = extra->s_ll;
+    a.s_t = extra->s_t;
+    a.s_tt = extra->s_tt;
+  }
+  const int R = mode == kHPair ? 0 : p->radius;
   switch (dtype) {
-    case ZDT_F32: return dispatch_h_f32(mode, R, seg, a, s);
-    case ZDT_F16: return dispatch_h_f16(mode, R, seg, a, s);
-    case ZDT_BF16: return dispatch_h_bf16(mode, R, seg, a, s);
+    case ZDT_F32: return dispatch_h_f32(mode, R, sp.seg, lps, a, s);
+    case ZDT_F16: return dispatch_h_f16(mode, R, sp.seg, lps, a, s);
+    case ZDT_BF16: return dispatch_h_bf16(mode, R, sp.seg, lps, a, s);
   }
   return fail(ZDT_EINVAL, "bad dtype %d", dtype);
 }
@@ -230,10 +253,7 @@ WsLayout ws_layout(const zdt_params* p) {
 }
 
 int run_hpair(const zdt_params* p, const uint8_t* guide, void* vol, float scale, int8_t* ex, hipStream_t s) {
-  const Split sp = h_split(p);
-  HArgs a = make_hargs(p, nullptr, nullptr, guide, vol, scale, sp);
-  a.ex = ex;
-  return dispatch_h(p->vol_dtype, kHPair, 0, sp.seg, a, s);
+  return run_h_mode(p, p->vol_dtype, kHPair, nullptr, nullptr, guide, vol, scale, ex, s);
 }
 
 int run_vpair(const zdt_params* p, const uint8_t* guide, void* vol, float scale, int8_t* ex, hipStream_t s) {
@@ -286,9 +306,7 @@ int zncc_cost_volume(const zdt_params* p, const uint8_t* left, const uint8_t* ri
   int rc = check_params(p, "zncc_cost_volume");
   if (rc) return rc;
   if (!left || !right || !cost) return fail(ZDT_EINVAL, "zncc_cost_volume: NULL image or volume pointer");
-  const Split sp = h_split(p);
-  return dispatch_h(p->vol_dtype, kCost, p->radius, sp.seg, make_hargs(p, left, right, nullptr, cost, 1.0f, sp),
-                    (hipStream_t)stream);
+  return run_h_mode(p, p->vol_dtype, kCost, left, right, nullptr, cost, 1.0f, nullptr, (hipStream_t)stream);
 }
 
 int zncc_window_sums(const zdt_params* p, const uint8_t* left, const uint8_t* right, int32_t* s_l, int32_t* s_ll,
@@ -296,14 +314,13 @@ int zncc_window_sums(const zdt_params* p, const uint8_t* left, const uint8_t* ri
   int rc = check_params(p, "zncc_window_sums");
   if (rc) return rc;
   if (!left || !right) return fail(ZDT_EINVAL, "zncc_window_sums: NULL image pointer");
-  const Split sp = h_split(p);
-  HArgs a = make_hargs(p, left, right, nullptr, nullptr, 1.0f, sp);
-  a.s_rt = s_rt;
-  a.s_l = s_l;
-  a.s_ll = s_ll;
-  a.s_t = s_t;
-  a.s_tt = s_tt;
-  return dispatch_h(ZDT_F32, kSums, p->radius, sp.seg, a, (hipStream_t)stream);
+  HArgs sums{};
+  sums.s_rt = s_rt;
+  sums.s_l = s_l;
+  sums.s_ll = s_ll;
+  sums.s_t = s_t;
+  sums.s_tt = s_tt;
+  return run_h_mode(p, ZDT_F32, kSums, left, right, nullptr, nullptr, 1.0f, nullptr, (hipStream_t)stream, &sums);
 }
 
 int dt_aggregate(const zdt_params* p, const uint8_t* guide, void* cost, double* applied_scale, void* stream) {
@@ -335,10 +352,8 @@ int stereo_solve(const zdt_params* p, const uint8_t* left, const uint8_t* right,
     return fail(ZDT_EINVAL, "stereo_solve: NULL image, disparity or volume pointer");
   hipStream_t s = (hipStream_t)stream;
   const uint8_t* guide = (p->flags & ZDT_FLAG_GUIDE_TARGET) ? right : left;
-  const Split hs = h_split(p);
   if (p->dt_iters == 0) {
-    if ((rc = dispatch_h(p->vol_dtype, kCost, p->radius, hs.seg, make_hargs(p, left, right, nullptr, vol, 1.0f, hs), s)))
-      return rc;
+    if ((rc = run_h_mode(p, p->vol_dtype, kCost, left, right, nullptr, vol, 1.0f, nullptr, s))) return rc;
     return dispatch_wta(p->vol_dtype, vol, p->width * p->height, p->max_disp, disp, s);
   }
   const WsLayout L = ws_layout(p);
@@ -349,9 +364,7 @@ int stereo_solve(const zdt_params* p, const uint8_t* left, const uint8_t* right,
   const float sc = ex ? 1.0f : pair_scale(p);
   // sweep 1: cost fused with L, R; then U, D.  Sweeps 2..I: L, R; U, D.  The
   // last U, D pair carries the WTA and writes no volume.
-  HArgs a = make_hargs(p, left, right, guide, vol, sc, hs);
-  a.ex = ex;
-  if ((rc = dispatch_h(p->vol_dtype, kCostHPair, p->radius, hs.seg, a, s))) return rc;
+  if ((rc = run_h_mode(p, p->vol_dtype, kCostHPair, left, right, guide, vol, sc, ex, s))) return rc;
   for (int it = 0; it < p->dt_iters; ++it) {
     if (it > 0 && (rc = run_hpair(p, guide, vol, sc, ex, s))) return rc;
     if (it + 1 < p->dt_iters) {

@@ -146,18 +146,29 @@ def main():
     forms["unfused_f32"] = {"ms_per_step": round(ms_u, 5), "gcost_evals_per_s": round(nvol / (ms_u * 1e-3) / 1e9, 3),
                             "fps": round(1000.0 / ms_u, 1)}
 
-    # per-kernel HIP-event times over the timed steps of the FP32 form
-    solver, disp = solvers["f32"]
-    for _ in range(args.warmup):
-        solver(L, Rt, disp)
-    torch.cuda.synchronize()
-    zdt.profile_enable(True)
-    for _ in range(args.steps):
-        solver(L, Rt, disp)
-    torch.cuda.synchronize()
-    kt = zdt.profile_collect()
-    zdt.profile_enable(False)
-    kernels = {k: {"avg_us": round(1e3 * ms / n, 3), "launches": n} for k, (ms, n) in kt.items()}
+    # per-kernel HIP-event times (recorded on the launch stream) over timed steps
+    def kernel_times(name):
+        solver, disp = solvers[name]
+        for _ in range(args.warmup):
+            solver(L, Rt, disp)
+        torch.cuda.synchronize()
+        zdt.profile_enable(True)
+        for _ in range(args.steps):
+            solver(L, Rt, disp)
+        torch.cuda.synchronize()
+        kt = zdt.profile_collect()
+        zdt.profile_enable(False)
+        s = 4 if name == "f32" else 2
+        ks = {k: {"avg_us": round(1e3 * ms / n, 3), "launches": n} for k, (ms, n) in kt.items()}
+        for k in ks:
+            b = algorithmic_bytes(k, s)
+            if b:
+                ks[k]["GBps"] = round(b / (ks[k]["avg_us"] * 1e-6) / 1e9, 1)
+        return kt, ks
+
+    kt, kernels = kernel_times("f32")
+    kernels_f16 = kernel_times("f16")[1]
+    kernels_bf16 = kernel_times("bf16")[1]
     dom = max(kt, key=lambda k: kt[k][0])
     avg_s = kt[dom][0] / kt[dom][1] * 1e-3
     abytes = algorithmic_bytes(dom, 4)
@@ -166,10 +177,6 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes": abytes, "avg_us": round(avg_s * 1e6, 3)}
-    for k in kernels:
-        b = algorithmic_bytes(k, 4)
-        if b:
-            kernels[k]["GBps"] = round(b / (kernels[k]["avg_us"] * 1e-6) / 1e9, 1)
 
     cpu = None
     if not args.no_cpu:
@@ -184,7 +191,8 @@ def main():
         "config": {"workload": WORKLOAD, "width": W, "height": H, "max_disp": D, "window": 2 * R + 1,
                    "sigma_s": SIGMA_S, "sigma_r": SIGMA_R, "dt_iters": ITERS, "vol_dtype": "f32",
                    "parallelism": "single-gpu"},
-        "fps": f32["fps"], "forms": forms, "kernels_f32": kernels, "roofline": roofline, "cpu_baseline": cpu,
+        "fps": f32["fps"], "forms": forms, "kernels_f32": kernels, "kernels_f16": kernels_f16,
+        "kernels_bf16": kernels_bf16, "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(line))
 

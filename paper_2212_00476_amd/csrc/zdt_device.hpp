@@ -38,9 +38,15 @@ constexpr int kWave = 64;
 constexpr int kMaxWaves = 16;
 constexpr int kMaxSegs = 32;   // segments per H workgroup (LPS = 32: two per wave)
 constexpr int kExpBias = 14;   // FP16 working volume: value = fp16 * 2^(e - kExpBias)
+constexpr int kExpChunk = 32;  // disparities sharing one FP16 exponent (a half-wave)
 
 struct bf16 {
   uint16_t bits;
+};
+// FP16 element of a working volume that carries per-(pixel, 32-d chunk)
+// exponents (see "Narrow working volumes" below); stored like _Float16.
+struct f16x {
+  _Float16 h;
 };
 
 typedef __amdgpu_buffer_rsrc_t rsrc_t;
@@ -74,6 +80,15 @@ struct Elem<_Float16> {
   static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t voff, uint32_t soff, float v) {
     __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)v), r, (int)voff, (int)soff,
                                           0);
+  }
+};
+template <>
+struct Elem<f16x> {
+  static __device__ __forceinline__ float bload(rsrc_t r, uint32_t voff, uint32_t soff) {
+    return Elem<_Float16>::bload(r, voff, soff);
+  }
+  static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t voff, uint32_t soff, float v) {
+    Elem<_Float16>::bstore(r, voff, soff, v);
   }
 };
 template <>
@@ -135,12 +150,13 @@ __device__ __forceinline__ void reload_fence() { asm volatile("" ::: "memory"); 
 //   TS, TI [W+P]  target window sum and inverse deviation at x' = t-P-d0.
 //   WH[W+1]       W_L(x) for x in [0, W]; WH[0] = WH[W] = 0.
 //   EX, EX2 [16*64], EXS, EXS2 [kMaxSegs]   segment carries.
+//   XP[2][W]      exponents of the row's stored FP16 values, per 32-d chunk.
 // ---------------------------------------------------------------------------
 struct HLayout {
-  int nLP, nTP, nTS, oLP, oLS, oLI, oTP, oTS, oTI, oWH, oEX, oEXS, oEX2, oEXS2, words;
+  int nLP, nTP, nTS, oLP, oLS, oLI, oTP, oTS, oTI, oWH, oEX, oEXS, oEX2, oEXS2, oXP, words;
 };
 
-__host__ __device__ inline HLayout h_layout(int W, int R, int LPS, int pad, bool zncc, bool dt) {
+__host__ __device__ inline HLayout h_layout(int W, int R, int LPS, int pad, bool zncc, bool dt, bool scaled) {
   HLayout L{};
   const int NP = packs_of(R);
   L.nLP = W + 2 * R + pad;
@@ -161,6 +177,8 @@ __host__ __device__ inline HLayout h_layout(int W, int R, int LPS, int pad, bool
     L.oEXS = o; o += kMaxSegs;
     L.oEX2 = o; o += kMaxWaves * kWave;
     L.oEXS2 = o; o += kMaxSegs;
+    L.oXP = o;
+    if (scaled) o += 2 * (W + pad);  // FP16 exponents of the row, one line per half-wave chunk
   }
   L.words = o;
   return L;
@@ -180,8 +198,9 @@ struct HArgs {
   int32_t* s_ll;
   int32_t* s_t;
   int32_t* s_tt;
-  int8_t* ex;      // FP16 working volume: per-(pixel, 64-d chunk) exponent map, else NULL
+  int8_t* ex;      // FP16 working volume: per-(pixel, 32-d chunk) exponent map, else NULL
   int segl, nseg;  // segment length and number of segments of a row
+  int nchunks;     // disparity chunks of LPS lanes per row
 };
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
@@ -305,7 +324,7 @@ __device__ __forceinline__ float zncc_cost_from(uint32_t srt, int sl, float il, 
 
 // ---------------------------------------------------------------------------
 // Narrow working volumes.  An FP16 working volume (ex != NULL) stores each
-// (pixel, chunk of 64 disparities) with a shared power-of-two exponent e:
+// (pixel, chunk of 32 disparities) with a shared power-of-two exponent e:
 // value = fp16 * 2^(e - 14).  The exponent is chosen from the chunk's maximum so
 // that the largest value lands in [2^14, 2^15); rescaling by a power of two is
 // exact, so only the FP16 rounding remains.  Without it the DT's gain, which
@@ -324,10 +343,44 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
-// Exponent of the largest |v| of the wave (0 when every value is 0).
-__device__ __forceinline__ int wave_exponent(float v) {
-  const uint32_t m = wave_max_u32(__float_as_uint(v) & 0x7FFFFFFFu);
+// Minimum of a 32-bit key over the 64 lanes (result from lane 63).
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+  const int id = -1;  // identity for lanes without a source
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, 0xB1, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, 0x4E, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, 0x141, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, 0x140, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, 0x142, 0xA, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, 0x143, 0xC, 0xF, false));
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Exponent of the largest |v| over the lane's half-wave of 32 lanes (0 when
+// every value is 0).
+__device__ __forceinline__ int half_exponent(float v) {
+  uint32_t u = __float_as_uint(v) & 0x7FFFFFFFu;
+  u = max(u, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)u, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+  u = max(u, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)u, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+  u = max(u, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)u, 0x141, 0xF, 0xF, false));  // row_half_mirror
+  u = max(u, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)u, 0x140, 0xF, 0xF, false));  // row_mirror
+  u = max(u, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)u, 0x142, 0xA, 0xF, false));  // row_bcast:15
+  const uint32_t m0 = (uint32_t)__builtin_amdgcn_readlane((int)u, 31);
+  const uint32_t m1 = (uint32_t)__builtin_amdgcn_readlane((int)u, 63);
+  const uint32_t m = (threadIdx.x & 32) ? m1 : m0;
   return m ? (int)(m >> 23) - 127 : 0;
+}
+
+// H workgroups that hold the two halves of the same 128-byte lines (chunks 2p
+// and 2p+1 of a row) get linear ids L and L+8: workgroups are dispatched to the
+// 8 XCDs round-robin, so such a pair runs on one XCD and shares its L2.
+struct HTile {
+  int y, chunk;
+};
+__device__ __forceinline__ HTile h_tile(int L, int H, int nchunks) {
+  const int npairs = (nchunks + 1) / 2;
+  const int r = L & 15;
+  const int i = (L >> 4) * 8 + (r & 7);
+  return {i / npairs, 2 * (i % npairs) + (r >> 3)};
 }
 
 template <int R, int SEG, int LPS, typename T, int MODE>
@@ -338,11 +391,20 @@ __global__ __launch_bounds__(1024) void hpass_kernel(HArgs a) {
   constexpr int SPW = kWave / LPS;  // segments per wave
   constexpr bool kZncc = MODE != kHPair;
   constexpr bool kDT = MODE == kCostHPair || MODE == kHPair;
-  constexpr bool kHalf = std::is_same<T, _Float16>::value;
+  constexpr bool kHalf = std::is_same<T, f16x>::value;  // exponent-scaled FP16
   static_assert(LPS == 64 || LPS == 32, "lanes per segment");
-  static_assert(!(kHalf && LPS != 64), "FP16 exponents are per 64-lane wave");
   constexpr uint32_t kBytes = sizeof(T);
-  const int y = blockIdx.y, d0 = blockIdx.x * LPS;
+  int y, chunk;
+  if constexpr (kDT && kBytes == 2) {
+    const HTile t = h_tile(blockIdx.x, a.H, a.nchunks);
+    if (t.y >= a.H || t.chunk >= a.nchunks) return;  // padding of the paired grid
+    y = t.y;
+    chunk = t.chunk;
+  } else {
+    y = blockIdx.y;
+    chunk = blockIdx.x;
+  }
+  const int d0 = chunk * LPS;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int dloc = lane & (LPS - 1);
@@ -353,9 +415,18 @@ __global__ __launch_bounds__(1024) void hpass_kernel(HArgs a) {
   // Two segments per wave are only used when the row splits into full segments
   // of exactly SEG values (checked by the host), so every step is in the row.
   constexpr bool kFull = LPS == 32;
-  const HLayout lay = h_layout(W, R, LPS, SEG, kZncc, kDT);
+  const HLayout lay = h_layout(W, R, LPS, SEG, kZncc, kDT, kHalf);
   if constexpr (kZncc) stage_zncc<R, LPS>(a, lay, smem, y, d0, MODE);
   if constexpr (kDT) stage_row_weights(a, (float*)(smem + lay.oWH), y);
+  if constexpr (kHalf && MODE == kHPair) {
+    // exponents of the (one or two) 32-d chunks this workgroup's lanes hold
+    const int nck = (D + kExpChunk - 1) / kExpChunk;
+    int* XP = (int*)(smem + lay.oXP);
+    for (int h = 0; h < LPS / kExpChunk; ++h) {
+      const int8_t* er = a.ex + (size_t)y * W * nck + min(d0 / kExpChunk + h, nck - 1);
+      for (int x = threadIdx.x; x < W; x += blockDim.x) XP[h * (W + SEG) + x] = er[(size_t)x * nck];
+    }
+  }
   __syncthreads();
 
   // segment [x0, x0 + len)
@@ -419,9 +490,10 @@ __global__ __launch_bounds__(1024) void hpass_kernel(HArgs a) {
     float* EXS = (float*)(smem + lay.oEXS);
     float* EX2 = (float*)(smem + lay.oEX2);
     float* EXS2 = (float*)(smem + lay.oEXS2);
-    const bool scaled = kHalf && a.ex != nullptr;
-    const int nck = (D + kWave - 1) / kWave;
-    int8_t* exrow = scaled ? a.ex + (size_t)y * W * nck + blockIdx.x : nullptr;
+    constexpr bool scaled = kHalf;
+    const int nck = (D + kExpChunk - 1) / kExpChunk;
+    // this lane's exponents: row y, its 32-d chunk (written by lanes 0 and 32)
+    int8_t* exrow = scaled ? a.ex + (size_t)y * W * nck + min(d / kExpChunk, nck - 1) : nullptr;
     const float* wp = WH + x0;  // W_L at x0 + k; padded past the row
     float c[SEG];
     // ---- loop A: values of the segment + carry-free L pass (ell) and weight product P
@@ -457,14 +529,11 @@ __global__ __launch_bounds__(1024) void hpass_kernel(HArgs a) {
 #pragma unroll
       for (int k = 0; k < SEG; ++k) c[k] = Elem<T>::bload(vrs, voff, step_soff(k));
       __builtin_amdgcn_sched_barrier(0);
-      if (scaled) {
-#pragma unroll
-        for (int k = 0; k < SEG; ++k)
-          c[k] = ldexpf(c[k], (int)exrow[(size_t)(x0 + min(k, len - 1)) * nck] - kExpBias);
-      }
+      const int* xp = (const int*)(smem + lay.oXP) + (LPS == 64 ? lane / kExpChunk : 0) * (W + SEG) + x0;
 #pragma unroll
       for (int k = 0; k < SEG; ++k) {
         const bool in = k < len;
+        if constexpr (scaled) c[k] = ldexpf(c[k], xp[k] - kExpBias);
         const float w = wp[k];
         ell = in ? fmaf(w, ell, c[k]) : ell;
         P = in ? P * w : P;
@@ -513,10 +582,10 @@ __global__ __launch_bounds__(1024) void hpass_kernel(HArgs a) {
 #pragma unroll
     for (int k = 0; k < SEG; ++k) {
       float v = c[k] * a.out_scale;
-      if (scaled && k < len) {
-        const int e = wave_exponent(active ? v : 0.0f);
+      if (scaled && k < len) {  // scaled is a compile-time constant
+        const int e = half_exponent(active ? v : 0.0f);
         v = ldexpf(v, kExpBias - e);
-        if (lane == 0) exrow[(size_t)(x0 + k) * nck] = (int8_t)e;
+        if ((lane & (kExpChunk - 1)) == 0 && active) exrow[(size_t)(x0 + k) * nck] = (int8_t)e;
       }
       if (k < len && active) Elem<T>::bstore(vrs, voff, step_soff(k), v);
     }
@@ -538,9 +607,10 @@ struct VArgs {
   int segl, nw;
 };
 
-// WV[H+1] (+ SEG spare entries), EX/EX2 [16*64*DPL], EXS/EXS2 [16]
-__host__ __device__ inline int v_lds_words(int H, int SEG, int DPL) {
-  return (H + 1 + SEG) + 2 * (kMaxWaves * kWave * DPL + kMaxWaves);
+// WV[H+1] (+ SEG spare entries), EX/EX2 [16*64*DPL], EXS/EXS2 [16], and for
+// scaled FP16 XP[2][H + SEG], the column's exponents per half-wave chunk
+__host__ __device__ inline int v_lds_words(int H, int SEG, int DPL, bool scaled) {
+  return (H + 1 + SEG) + 2 * (kMaxWaves * kWave * DPL + kMaxWaves) + (scaled ? 2 * (H + SEG) : 0);
 }
 
 __device__ __forceinline__ float wave_min(float v) {
@@ -552,7 +622,8 @@ __device__ __forceinline__ float wave_min(float v) {
 template <int SEG, typename T, int DPL, bool WTA>
 __global__ __launch_bounds__(1024) void vpass_kernel(VArgs a) {
   extern __shared__ uint32_t smem[];
-  constexpr bool kHalf = std::is_same<T, _Float16>::value;
+  constexpr bool kHalf = std::is_same<T, f16x>::value;  // exponent-scaled FP16
+  static_assert(DPL == 1 || !kHalf, "FP16 exponents are per half-wave chunk");
   constexpr uint32_t kBytes = sizeof(T);
   const int chunk = blockIdx.x, x = blockIdx.y;
   const int d0 = chunk * kWave * DPL;
@@ -564,6 +635,15 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs a) {
   float* EXS = EX + kMaxWaves * kWave * DPL;
   float* EX2 = EXS + kMaxWaves;
   float* EXS2 = EX2 + kMaxWaves * kWave * DPL;
+  int* XP = (int*)(EXS2 + kMaxWaves);
+  if constexpr (kHalf) {
+    // exponents of the column's two 32-d chunks (one per half-wave)
+    const int nck = (D + kExpChunk - 1) / kExpChunk;
+    for (int h = 0; h < 2; ++h) {
+      const int ck = min(chunk * 2 + h, nck - 1);  // a half-wave past D reads any valid chunk
+      for (int y = threadIdx.x; y < H; y += blockDim.x) XP[h * (H + SEG) + y] = a.ex[((size_t)y * W + x) * nck + ck];
+    }
+  }
   for (int y = threadIdx.x; y <= H; y += blockDim.x)
     WV[y] = (y >= 1 && y < H) ? dt_weight(a.guide[(size_t)y * a.pitch + x], a.guide[(size_t)(y - 1) * a.pitch + x],
                                           a.inv_sigma_s, a.range_coef)
@@ -575,8 +655,9 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs a) {
   // buffer over the volume from column x on; every offset below stays inside it
   const rsrc_t vrs = make_rsrc((const char*)a.vol + (size_t)x * D * kBytes,
                                (uint32_t)((size_t)H * W * D * kBytes - (size_t)x * D * kBytes));
-  const bool scaled = kHalf && a.ex != nullptr;
-  const int nck = (D + kWave - 1) / kWave;
+  constexpr bool scaled = kHalf;
+  const int nck = (D + kExpChunk - 1) / kExpChunk;
+  const int* xp = XP + (lane / kExpChunk) * (H + SEG) + y0;  // this half-wave's exponents
   auto yat = [&](int k) -> int { return y0 + (k < len ? k : len - 1); };
   const float* wp = WV + y0;  // W_U at y0 + k; padded past the column
   bool act[DPL];
@@ -594,16 +675,7 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs a) {
 #pragma unroll
     for (int j = 0; j < DPL; ++j) c[j][k] = Elem<T>::bload(vrs, voff[j], (uint32_t)yat(k) * rowbytes);
   __builtin_amdgcn_sched_barrier(0);
-  if (scaled) {
-#pragma unroll
-    for (int j = 0; j < DPL; ++j) {
-      if (chunk * DPL + j >= nck) continue;  // no disparity of this lane group exists
-      const int8_t* ex = a.ex + (size_t)x * nck + chunk * DPL + j;
-#pragma unroll
-      for (int k = 0; k < SEG; ++k) c[j][k] = ldexpf(c[j][k], (int)ex[(size_t)yat(k) * W * nck] - kExpBias);
-    }
-  }
-  // ---- loop A: carry-free U pass
+  // ---- loop A: carry-free U pass (decoding scaled FP16 values on the way)
   float ell[DPL], P = 1.0f;
 #pragma unroll
   for (int j = 0; j < DPL; ++j) ell[j] = 0.0f;
@@ -611,6 +683,7 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs a) {
   for (int k = 0; k < SEG; ++k) {
     const bool in = k < len;
     const float w = wp[k];
+    if constexpr (scaled) c[0][k] = ldexpf(c[0][k], xp[k] - kExpBias);
 #pragma unroll
     for (int j = 0; j < DPL; ++j) ell[j] = in ? fmaf(w, ell[j], c[j][k]) : ell[j];
     P = in ? P * w : P;
@@ -689,33 +762,36 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs a) {
   if constexpr (!WTA) {
 #pragma unroll
     for (int j = 0; j < DPL; ++j) {
-      int8_t* ex = scaled ? a.ex + (size_t)x * nck + chunk * DPL + j : nullptr;
+      const int ck = chunk * 2 + lane / kExpChunk;  // this half-wave's 32-d chunk
+      int8_t* ex = scaled ? a.ex + (size_t)x * nck + min(ck, nck - 1) : nullptr;
 #pragma unroll
       for (int k = 0; k < SEG; ++k)
         if (k < len) {
           float v = c[j][k] * a.out_scale;
-          if (scaled) {
-            const int e = wave_exponent(act[j] ? v : 0.0f);
+          if constexpr (scaled) {
+            const int e = half_exponent(act[j] ? v : 0.0f);
             v = ldexpf(v, kExpBias - e);
-            if (lane == 0) ex[(size_t)(y0 + k) * W * nck] = (int8_t)e;
+            if ((lane & (kExpChunk - 1)) == 0 && ck < nck) ex[(size_t)(y0 + k) * W * nck] = (int8_t)e;
           }
           if (act[j]) Elem<T>::bstore(vrs, voff[j], (uint32_t)(y0 + k) * rowbytes, v);
         }
     }
   } else {
-    // argmin over the chunk's disparities, lowest d on ties (Eq. WTA1)
-    const float inf = __builtin_inff();
+    // argmin over the chunk's disparities, lowest d on ties (Eq. WTA1).  The
+    // aggregated costs are >= 0, so their bit patterns order like the values
+    // (|.| folds a -0 onto +0); idle lanes hold +inf.
+    const uint32_t kInf = 0x7F800000u;
 #pragma unroll
     for (int k = 0; k < SEG; ++k)
       if (k < len) {
-        float v[DPL];
-        float best = inf;
+        uint32_t v[DPL];
+        uint32_t best = kInf;
 #pragma unroll
         for (int j = 0; j < DPL; ++j) {
-          v[j] = act[j] ? c[j][k] : inf;
-          best = fminf(best, v[j]);
+          v[j] = act[j] ? (__float_as_uint(c[j][k]) & 0x7FFFFFFFu) : kInf;
+          best = min(best, v[j]);
         }
-        const float m = wave_min(best);
+        const uint32_t m = wave_min_u32(best);
         int dbest = 0;
 #pragma unroll
         for (int j = DPL - 1; j >= 0; --j) {
@@ -727,7 +803,7 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs a) {
           if (a.disp) {
             a.disp[p] = dbest;
           } else {
-            a.part_val[(size_t)chunk * W * H + p] = m;
+            a.part_val[(size_t)chunk * W * H + p] = __uint_as_float(m);
             a.part_idx[(size_t)chunk * W * H + p] = dbest;
           }
         }

@@ -34,9 +34,10 @@ int launch(const char* name, Kernel kernel, dim3 grid, dim3 block, size_t lds, h
   return ZDT_OK;
 }
 
-// Segment lengths (values per lane) compiled for the H and V passes.  H
-// passes over FP32 volumes give each wave two segments of 32 disparities (a
-// 128-byte line per half-wave); 16-bit volumes one segment of 64 disparities.
+// Segment lengths (values per lane) compiled for the H and V passes.  H pairs
+// give each wave two segments of 32 disparities when the row splits into full
+// segments (a 128-byte line per half-wave for FP32, half a line for 16-bit
+// volumes, whose two chunks then share an XCD), else one of 64 disparities.
 constexpr int kHSegs32[] = {8, 20, 40};    // LPS = 32: up to 32 segments per row
 constexpr int kHSegs64[] = {16, 40, 80};   // LPS = 64: up to 16 segments per row
 constexpr int kVSegs[] = {8, 12, 24, 48, 72};
@@ -49,7 +50,8 @@ inline int h_full_seg32(int W) {
   return 0;
 }
 inline int h_lps(int dtype, int mode, int W) {
-  return (dtype == ZDT_F32 && (mode == kCostHPair || mode == kHPair) && h_full_seg32(W)) ? 32 : 64;
+  (void)dtype;
+  return ((mode == kCostHPair || mode == kHPair) && h_full_seg32(W)) ? 32 : 64;
 }
 
 // Kernel dispatch, one set per volume element type (defined in zdt_inst_*.hip).
@@ -60,6 +62,7 @@ inline int h_lps(int dtype, int mode, int W) {
 ZDT_DECLARE_DISPATCH(f32)
 ZDT_DECLARE_DISPATCH(f16)
 ZDT_DECLARE_DISPATCH(bf16)
+ZDT_DECLARE_DISPATCH(f16x)
 #undef ZDT_DECLARE_DISPATCH
 
 }  // namespace zdt

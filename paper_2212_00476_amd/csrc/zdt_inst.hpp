@@ -10,12 +10,20 @@ namespace inst {
 
 template <int R, int SEG, int LPS, typename T, int MODE>
 int run_h(const HArgs& a, hipStream_t s) {
-  const HLayout lay = h_layout(a.W, R, LPS, SEG, MODE != kHPair, MODE == kCostHPair || MODE == kHPair);
+  const HLayout lay = h_layout(a.W, R, LPS, SEG, MODE != kHPair, MODE == kCostHPair || MODE == kHPair,
+                              std::is_same<T, f16x>::value);
   static const char* const names[] = {"zncc_sums", "zncc_cost", "zncc_hpair", "dt_hpair"};
   const int spw = kWave / LPS;
   const int nw = (a.nseg + spw - 1) / spw;
-  return launch(names[MODE], hpass_kernel<R, SEG, LPS, T, MODE>, dim3((a.D + LPS - 1) / LPS, a.H), dim3(kWave * nw),
-                (size_t)lay.words * 4, s, a);
+  HArgs b = a;
+  b.nchunks = (a.D + LPS - 1) / LPS;
+  dim3 grid(b.nchunks, a.H);
+  if constexpr ((MODE == kCostHPair || MODE == kHPair) && sizeof(T) == 2) {
+    // 1-D grid with the chunk pairs of a row on one XCD (see h_tile)
+    const int items = a.H * ((b.nchunks + 1) / 2);
+    grid = dim3((unsigned)((items + 7) / 8 * 16));
+  }
+  return launch(names[MODE], hpass_kernel<R, SEG, LPS, T, MODE>, grid, dim3(kWave * nw), (size_t)lay.words * 4, s, b);
 }
 
 template <int R, int LPS, typename T, int MODE>
@@ -54,7 +62,7 @@ int run_h_radius(int R, int seg, const HArgs& a, hipStream_t s) {
 template <int SEG, typename T, int DPL, bool WTA>
 int run_v(const VArgs& a, int nchunks, hipStream_t s) {
   return launch(WTA ? "dt_vpair_wta" : "dt_vpair", vpass_kernel<SEG, T, DPL, WTA>, dim3(nchunks, a.W),
-                dim3(kWave * a.nw), (size_t)v_lds_words(a.H, SEG, DPL) * 4, s, a);
+                dim3(kWave * a.nw), (size_t)v_lds_words(a.H, SEG, DPL, std::is_same<T, f16x>::value) * 4, s, a);
 }
 
 template <typename T, int DPL, bool WTA>
@@ -80,18 +88,17 @@ namespace zdt {
 int ZDT_CAT(dispatch_h_, ZDT_SUFFIX)(int mode, int R, int seg, int lps, const HArgs& a, hipStream_t s) {
   using T = ZDT_ELEM;
   constexpr bool f32 = std::is_same<T, float>::value;
+  constexpr bool f16x_ = std::is_same<T, f16x>::value;
   switch (mode) {
-    case kCost: return inst::run_h_radius<T, kCost, 64>(R, seg, a, s);
+    case kCost:
+      if constexpr (!f16x_) return inst::run_h_radius<T, kCost, 64>(R, seg, a, s);
+      break;
     case kCostHPair:
-      if constexpr (f32) {
-        if (lps == 32) return inst::run_h_radius<T, kCostHPair, 32>(R, seg, a, s);
-      }
+      if (lps == 32) return inst::run_h_radius<T, kCostHPair, 32>(R, seg, a, s);
       if (lps == 64) return inst::run_h_radius<T, kCostHPair, 64>(R, seg, a, s);
       break;
     case kHPair:
-      if constexpr (f32) {
-        if (lps == 32) return inst::run_h_seg<0, 32, T, kHPair>(seg, a, s);
-      }
+      if (lps == 32) return inst::run_h_seg<0, 32, T, kHPair>(seg, a, s);
       if (lps == 64) return inst::run_h_seg<0, 64, T, kHPair>(seg, a, s);
       break;
     case kSums:
@@ -103,24 +110,21 @@ int ZDT_CAT(dispatch_h_, ZDT_SUFFIX)(int mode, int R, int seg, int lps, const HA
 
 int ZDT_CAT(dispatch_v_, ZDT_SUFFIX)(int seg, int dpl, bool wta, const VArgs& a, int nchunks, hipStream_t s) {
   using T = ZDT_ELEM;
+  if (dpl != 1) return fail(ZDT_EUNSUPPORTED, "V pass with %d disparities per lane", dpl);
   if (!wta) return inst::run_v_seg<T, 1, false>(seg, a, nchunks, s);
-  if (dpl == 2) {
-    switch (seg) {
-      case 8: return inst::run_v<8, T, 2, true>(a, nchunks, s);
-      case 12: return inst::run_v<12, T, 2, true>(a, nchunks, s);
-      case 24: return inst::run_v<24, T, 2, true>(a, nchunks, s);
-    }
-    return fail(ZDT_EUNSUPPORTED, "no two-disparity-per-lane V instance for segment length %d", seg);
-  }
   return inst::run_v_seg<T, 1, true>(seg, a, nchunks, s);
 }
 
 int ZDT_CAT(dispatch_wta_, ZDT_SUFFIX)(const void* vol, int npix, int D, int32_t* disp, hipStream_t s) {
   using T = ZDT_ELEM;
+  if constexpr (std::is_same<T, f16x>::value) {
+    return fail(ZDT_EUNSUPPORTED, "no standalone WTA over an exponent-scaled volume");
+  } else {
   const int threads = 256, waves_per_block = threads / kWave;
   int blocks = (npix + waves_per_block - 1) / waves_per_block;
   if (blocks > 8192) blocks = 8192;
   return launch("wta", wta_kernel<T>, dim3(blocks), dim3(threads), 0, s, (const T*)vol, npix, D, disp);
+  }
 }
 
 }  // namespace zdt

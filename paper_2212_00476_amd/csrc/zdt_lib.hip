@@ -192,7 +192,8 @@ int run_h_mode(const zdt_params* p, int dtype, int mode, const uint8_t* left, co
   const int R = mode == kHPair ? 0 : p->radius;
   switch (dtype) {
     case ZDT_F32: return dispatch_h_f32(mode, R, sp.seg, lps, a, s);
-    case ZDT_F16: return dispatch_h_f16(mode, R, sp.seg, lps, a, s);
+    case ZDT_F16:
+      return ex ? dispatch_h_f16x(mode, R, sp.seg, lps, a, s) : dispatch_h_f16(mode, R, sp.seg, lps, a, s);
     case ZDT_BF16: return dispatch_h_bf16(mode, R, sp.seg, lps, a, s);
   }
   return fail(ZDT_EINVAL, "bad dtype %d", dtype);
@@ -201,7 +202,8 @@ int run_h_mode(const zdt_params* p, int dtype, int mode, const uint8_t* left, co
 int dispatch_v(int dtype, int seg, int dpl, bool wta, const VArgs& a, int nchunks, hipStream_t s) {
   switch (dtype) {
     case ZDT_F32: return dispatch_v_f32(seg, dpl, wta, a, nchunks, s);
-    case ZDT_F16: return dispatch_v_f16(seg, dpl, wta, a, nchunks, s);
+    case ZDT_F16:
+      return a.ex ? dispatch_v_f16x(seg, dpl, wta, a, nchunks, s) : dispatch_v_f16(seg, dpl, wta, a, nchunks, s);
     case ZDT_BF16: return dispatch_v_bf16(seg, dpl, wta, a, nchunks, s);
   }
   return fail(ZDT_EINVAL, "bad dtype %d", dtype);
@@ -222,9 +224,10 @@ struct VWta {
   int dpl, nchunks;
 };
 VWta v_wta_shape(const zdt_params* p, int seg) {
-  const int D = p->max_disp;
-  const int dpl = (D > kWave && seg <= 24) ? 2 : 1;
-  return {dpl, (D + kWave * dpl - 1) / (kWave * dpl)};
+  (void)seg;
+  // one disparity per lane keeps the kernel at two workgroups per CU; several
+  // 64-disparity chunks are combined by a small second kernel
+  return {1, (p->max_disp + kWave - 1) / kWave};
 }
 
 // Workspace of stereo_solve: the FP16 exponent map, then the WTA partial minima.
@@ -235,7 +238,7 @@ size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 WsLayout ws_layout(const zdt_params* p) {
   WsLayout L{};
   const size_t npix = (size_t)p->width * p->height;
-  const size_t nck = (size_t)(p->max_disp + kWave - 1) / kWave;
+  const size_t nck = (size_t)(p->max_disp + kExpChunk - 1) / kExpChunk;
   size_t o = 0;
   if (p->vol_dtype == ZDT_F16 && p->dt_iters > 0) {
     L.ex = o;

@@ -277,6 +277,29 @@ def test_stereo_solve_odd_shapes_fp32(shape, iters):
     assert ok.all(), slack[~ok].max()
 
 
+NARROW = [(160, 48, 128, 4), (96, 40, 96, 2), (200, 64, 200, 3), (640, 32, 130, 4), (37, 23, 70, 1)]
+
+
+@pytest.mark.parametrize("dtype", [zdt.ZDT_F16, zdt.ZDT_BF16], ids=["f16", "bf16"])
+@pytest.mark.parametrize("shape", NARROW, ids=ids(NARROW))
+def test_stereo_solve_narrow_several_chunks(shape, dtype):
+    """16-bit working volumes with several 32- and 64-disparity chunks (odd
+    counts included): disparities agree with the FP64 oracle up to the
+    storage type's rounding."""
+    W, H, D, r = shape
+    note(f"stereo_solve narrow {shape} dtype={dtype}")
+    pr = pair_for(W, H, D, seed=11)
+    disp = _solve_gpu(pr, D, r, dtype)
+    o_disp, cagg = oracle.stereo_solve(pr.left, pr.right, D, r, 20.0, 0.1, 3, keep_volume=True)
+    mism = (disp != o_disp).mean()
+    slack, _ = _near_tie_ok(disp, cagg)
+    rel = (slack / np.maximum(np.abs(cagg).max(axis=2), 1e-300)).max()
+    note(f"  mismatch {100 * mism:.4f} %, worst relative slack {rel:.2e}")
+    # a flipped pixel must be a near-tie at the storage precision
+    assert rel <= (5e-3 if dtype == zdt.ZDT_F16 else 4e-2)
+    assert mism <= (5e-3 if dtype == zdt.ZDT_F16 else 3e-2)
+
+
 def test_fused_equals_unfused_fp32():
     """stereo_solve (cost fused into the first H pair, WTA into the last V
     pair) equals zncc_cost_volume + dt_aggregate + wta_disparity bit for bit."""

@@ -51,9 +51,16 @@ struct f16x {
 
 typedef __amdgpu_buffer_rsrc_t rsrc_t;
 
-// Raw buffer over [base, base + bytes).
+// Raw buffer over [base, base + bytes).  base and bytes are workgroup-uniform;
+// passing them through readfirstlane lets the compiler keep the descriptor in
+// SGPRs (otherwise every access is wrapped in a waterfall loop).
 __device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+  const uint64_t b = (uint64_t)base;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+  const int n = __builtin_amdgcn_readfirstlane((int)bytes);
+  void* p = (void*)(((uint64_t)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, n, 0x00020000);
 }
 
 template <typename T>
@@ -619,7 +626,8 @@ __device__ __forceinline__ float wave_min(float v) {
   return v;
 }
 
-template <int SEG, typename T, int DPL, bool WTA>
+// FULL: every wave's segment holds exactly SEG rows (checked by the host).
+template <int SEG, bool FULL, typename T, int DPL, bool WTA>
 __global__ __launch_bounds__(1024) void vpass_kernel(VArgs a) {
   extern __shared__ uint32_t smem[];
   constexpr bool kHalf = std::is_same<T, f16x>::value;  // exponent-scaled FP16
@@ -650,7 +658,7 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs a) {
                               : 0.0f;
   __syncthreads();
   const int y0 = wave * a.segl;
-  const int len = min(a.segl, H - y0);  // >= 1, wave-uniform
+  const int len = FULL ? SEG : min(a.segl, H - y0);  // >= 1, wave-uniform
   const uint32_t rowbytes = (uint32_t)W * D * kBytes;
   // buffer over the volume from column x on; every offset below stays inside it
   const rsrc_t vrs = make_rsrc((const char*)a.vol + (size_t)x * D * kBytes,

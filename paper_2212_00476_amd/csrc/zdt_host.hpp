@@ -38,10 +38,10 @@ int launch(const char* name, Kernel kernel, dim3 grid, dim3 block, size_t lds, h
 // give each wave two segments of 32 disparities when the row splits into full
 // segments (a 128-byte line per half-wave for FP32, half a line for 16-bit
 // volumes, whose two chunks then share an XCD), else one of 64 disparities.
-constexpr int kHSegs32[] = {8, 20, 40};    // LPS = 32: up to 32 segments per row
-constexpr int kHSegs64[] = {16, 40, 80};   // LPS = 64: up to 16 segments per row
+constexpr int kHSegs32[] = {8, 20, 40, 60};  // LPS = 32: up to 32 segments per row
+constexpr int kHSegs64[] = {16, 40, 80};      // LPS = 64: up to 16 segments per row
 constexpr int kVSegs[] = {8, 12, 24, 48, 72};
-constexpr int kNumHSegs = 3, kNumVSegs = 5;
+constexpr int kNumHSegs64 = 3, kNumVSegs = 5;
 // FP32 H pairs take two segments per wave when the row splits into an even
 // number (<= 32) of full segments of a compiled length; otherwise one.
 inline int h_full_seg32(int W) {

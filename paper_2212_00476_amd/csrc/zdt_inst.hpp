@@ -33,6 +33,7 @@ int run_h_seg(int seg, const HArgs& a, hipStream_t s) {
       case 8: return run_h<R, 8, LPS, T, MODE>(a, s);
       case 20: return run_h<R, 20, LPS, T, MODE>(a, s);
       case 40: return run_h<R, 40, LPS, T, MODE>(a, s);
+      case 60: return run_h<R, 60, LPS, T, MODE>(a, s);
     }
   } else {
     switch (seg) {
@@ -59,20 +60,19 @@ int run_h_radius(int R, int seg, const HArgs& a, hipStream_t s) {
   return fail(ZDT_EUNSUPPORTED, "no H-pass instance for radius %d", R);
 }
 
-template <int SEG, typename T, int DPL, bool WTA>
+template <int SEG, bool FULL, typename T, int DPL, bool WTA>
 int run_v(const VArgs& a, int nchunks, hipStream_t s) {
-  return launch(WTA ? "dt_vpair_wta" : "dt_vpair", vpass_kernel<SEG, T, DPL, WTA>, dim3(nchunks, a.W),
+  return launch(WTA ? "dt_vpair_wta" : "dt_vpair", vpass_kernel<SEG, FULL, T, DPL, WTA>, dim3(nchunks, a.W),
                 dim3(kWave * a.nw), (size_t)v_lds_words(a.H, SEG, DPL, std::is_same<T, f16x>::value) * 4, s, a);
 }
 
 template <typename T, int DPL, bool WTA>
-int run_v_seg(int seg, const VArgs& a, int nchunks, hipStream_t s) {
+int run_v_seg(int seg, bool full, const VArgs& a, int nchunks, hipStream_t s) {
   switch (seg) {
-    case 8: return run_v<8, T, DPL, WTA>(a, nchunks, s);
-    case 12: return run_v<12, T, DPL, WTA>(a, nchunks, s);
-    case 24: return run_v<24, T, DPL, WTA>(a, nchunks, s);
-    case 48: return run_v<48, T, DPL, WTA>(a, nchunks, s);
-    case 72: return run_v<72, T, DPL, WTA>(a, nchunks, s);
+#define ZDT_CASE(SS) \
+  case SS: return full ? run_v<SS, true, T, DPL, WTA>(a, nchunks, s) : run_v<SS, false, T, DPL, WTA>(a, nchunks, s);
+    ZDT_CASE(8) ZDT_CASE(12) ZDT_CASE(24) ZDT_CASE(48) ZDT_CASE(72)
+#undef ZDT_CASE
   }
   return fail(ZDT_EUNSUPPORTED, "no V-pass instance for segment length %d", seg);
 }
@@ -111,8 +111,9 @@ int ZDT_CAT(dispatch_h_, ZDT_SUFFIX)(int mode, int R, int seg, int lps, const HA
 int ZDT_CAT(dispatch_v_, ZDT_SUFFIX)(int seg, int dpl, bool wta, const VArgs& a, int nchunks, hipStream_t s) {
   using T = ZDT_ELEM;
   if (dpl != 1) return fail(ZDT_EUNSUPPORTED, "V pass with %d disparities per lane", dpl);
-  if (!wta) return inst::run_v_seg<T, 1, false>(seg, a, nchunks, s);
-  return inst::run_v_seg<T, 1, true>(seg, a, nchunks, s);
+  const bool full = a.segl == seg && a.nw * seg == a.H;
+  if (!wta) return inst::run_v_seg<T, 1, false>(seg, full, a, nchunks, s);
+  return inst::run_v_seg<T, 1, true>(seg, full, a, nchunks, s);
 }
 
 int ZDT_CAT(dispatch_wta_, ZDT_SUFFIX)(const void* vol, int npix, int D, int32_t* disp, hipStream_t s) {

@@ -90,8 +90,9 @@ int check_params(const zdt_params* p, const char* who) {
   if (nvol >= (1LL << 31)) return fail(ZDT_EUNSUPPORTED, "%s: W*H*D = %lld exceeds 2^31-1 elements", who, nvol);
   if ((long long)nvol * (long long)dtype_size(p->vol_dtype) >= (1LL << 32))
     return fail(ZDT_EUNSUPPORTED, "%s: the volume must stay below 4 GiB (32-bit buffer offsets)", who);
-  if (p->width > kMaxWaves * kHSegs64[kNumHSegs - 1])
-    return fail(ZDT_EUNSUPPORTED, "%s: width %d > %d", who, p->width, kMaxWaves * kHSegs64[kNumHSegs - 1]);
+  if (p->width > kMaxWaves * kHSegs64[kNumHSegs64 - 1] && !h_full_seg32(p->width))
+    return fail(ZDT_EUNSUPPORTED, "%s: width %d > %d and not a multiple of 64 up to %d", who, p->width,
+                kMaxWaves * kHSegs64[kNumHSegs64 - 1], 2 * kMaxWaves * kHSegs32[3]);
   if (p->height > kMaxWaves * kVSegs[kNumVSegs - 1])
     return fail(ZDT_EUNSUPPORTED, "%s: height %d > %d", who, p->height, kMaxWaves * kVSegs[kNumVSegs - 1]);
   return ZDT_OK;
@@ -113,12 +114,16 @@ Split split_line(int n, const int* segs, int nsegs, int maxseg) {
   return {0, 0, 0};
 }
 
-Split h_split(const zdt_params* p, int lps) {
+Split h_split(const zdt_params* p, int lps, int mode) {
+  if (mode == kSums || mode == kCost) {  // streamed: any segment length, 16 waves
+    const int segl = (p->width + kMaxWaves - 1) / kMaxWaves;
+    return {0, segl, (p->width + segl - 1) / segl};
+  }
   if (lps == 32) {
     const int seg = h_full_seg32(p->width);
     return {seg, seg, p->width / seg};
   }
-  return split_line(p->width, kHSegs64, kNumHSegs, kMaxWaves);
+  return split_line(p->width, kHSegs64, kNumHSegs64, kMaxWaves);
 }
 Split v_split(const zdt_params* p) { return split_line(p->height, kVSegs, kNumVSegs, kMaxWaves); }
 
@@ -179,7 +184,7 @@ VArgs make_vargs(const zdt_params* p, const uint8_t* guide, void* vol, float out
 int run_h_mode(const zdt_params* p, int dtype, int mode, const uint8_t* left, const uint8_t* right,
                const uint8_t* guide, void* vol, float scale, int8_t* ex, hipStream_t s, HArgs* extra = nullptr) {
   const int lps = h_lps(dtype, mode, p->width);
-  const Split sp = h_split(p, lps);
+  const Split sp = h_split(p, lps, mode);
   HArgs a = make_hargs(p, left, right, guide, vol, scale, sp);
   a.ex = ex;
   if (extra) {

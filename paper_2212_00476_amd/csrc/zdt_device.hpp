@@ -146,6 +146,34 @@ __device__ __forceinline__ void step_fence(int k, V&... v) {
 // Re-read LDS weights in each pass instead of keeping a line of them live.
 __device__ __forceinline__ void reload_fence() { asm volatile("" ::: "memory"); }
 
+// Exact value entering segment `seg` of a split first-order recursion.
+// Segment s maps an incoming value c to A[s] * c + B[s * ncol + col] (its weight
+// product and its carry-free end value); the carry is the composition, in
+// recursion order, of the segments before `seg` (0..seg-1; REV: n-1 down to
+// seg+1) applied to 0.  The loads of a block of kCarryBlock segments are issued
+// together, so a block costs one LDS round trip instead of one per segment.
+// `max_count` is a wave-uniform bound on the number of segments to compose.
+constexpr int kCarryBlock = 4;
+template <bool REV>
+__device__ __forceinline__ float carry_in(const float* B, const float* A, int seg, int n, int ncol, int col,
+                                          int max_count) {
+  const int count = REV ? n - 1 - seg : seg;
+  float carry = 0.0f;
+  for (int t0 = 0; t0 < max_count; t0 += kCarryBlock) {
+    float a[kCarryBlock], b[kCarryBlock];
+#pragma unroll
+    for (int i = 0; i < kCarryBlock; ++i) {
+      const int t = min(t0 + i, n - 1);  // position in recursion order (clamped; unused past count)
+      const int s = REV ? n - 1 - t : t;
+      a[i] = A[s];
+      b[i] = B[s * ncol + col];
+    }
+#pragma unroll
+    for (int i = 0; i < kCarryBlock; ++i) carry = (t0 + i < count) ? fmaf(a[i], carry, b[i]) : carry;
+  }
+  return carry;
+}
+
 // ---------------------------------------------------------------------------
 // LDS layout of hpass_kernel, in 32-bit words (P = LPS - 1); every line array
 // below is followed by `pad` (= SEG) spare entries.
@@ -163,7 +191,7 @@ struct HLayout {
   int nLP, nTP, nTS, oLP, oLS, oLI, oTP, oTS, oTI, oWH, oEX, oEXS, oEX2, oEXS2, oXP, words;
 };
 
-__host__ __device__ inline HLayout h_layout(int W, int R, int LPS, int pad, bool zncc, bool dt, bool scaled) {
+__host__ __device__ constexpr HLayout h_layout(int W, int R, int LPS, int pad, bool zncc, bool dt, bool scaled) {
   HLayout L{};
   const int NP = packs_of(R);
   L.nLP = W + 2 * R + pad;
@@ -390,8 +418,17 @@ __device__ __forceinline__ HTile h_tile(int L, int H, int nchunks) {
   return {i / npairs, 2 * (i % npairs) + (r >> 3)};
 }
 
+// Waves per SIMD the register allocator is asked to allow.  H pairs with two
+// segments of up to 40 values per wave are held to 64 VGPRs (spilling a few
+// words at most), so two 1024-lane workgroups share a CU and one's staging and
+// exchanges overlap the other's recursions; the rest get up to 128 VGPRs.
+template <int R, int SEG, int LPS, int MODE>
+constexpr int h_waves_per_eu() {
+  return ((MODE == kCostHPair || MODE == kHPair) && LPS == 32 && SEG <= 40) ? 8 : 4;
+}
+
 template <int R, int SEG, int LPS, typename T, int MODE>
-__global__ __launch_bounds__(1024) void hpass_kernel(HArgs a) {
+__global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void hpass_kernel(HArgs a) {
   extern __shared__ uint32_t smem[];
   constexpr int NW = 2 * R + 1;  // window side
   constexpr int N = NW * NW;
@@ -422,7 +459,11 @@ __global__ __launch_bounds__(1024) void hpass_kernel(HArgs a) {
   // Two segments per wave are only used when the row splits into full segments
   // of exactly SEG values (checked by the host), so every step is in the row.
   constexpr bool kFull = LPS == 32;
-  const HLayout lay = h_layout(W, R, LPS, SEG, kZncc, kDT, kHalf);
+  // Register-resident modes size LDS for the widest row of the instance, so the
+  // array offsets are compile-time constants (one base register per index
+  // pattern instead of one per array); streaming modes size it for this row.
+  constexpr int kWMax = (kWave / LPS) * kMaxWaves * SEG;
+  const HLayout lay = h_layout(kDT ? kWMax : W, R, LPS, SEG, kZncc, kDT, kHalf);
   if constexpr (kZncc) stage_zncc<R, LPS>(a, lay, smem, y, d0, MODE);
   if constexpr (kDT) stage_row_weights(a, (float*)(smem + lay.oWH), y);
   if constexpr (kHalf && MODE == kHPair) {
@@ -506,6 +547,9 @@ __global__ __launch_bounds__(1024) void hpass_kernel(HArgs a) {
     // ---- loop A: values of the segment + carry-free L pass (ell) and weight product P
     float ell = 0.0f, P = 1.0f;
     if constexpr (MODE == kCostHPair) {
+      // Two sweeps over the segment keep the peak register count down: first
+      // the window cross-sums S_RT (running over a ring of column sums), held
+      // as bits in c[], then the costs and the carry-free L pass.
       uint32_t ring[NW];
       uint32_t S = 0;
 #pragma unroll
@@ -515,20 +559,29 @@ __global__ __launch_bounds__(1024) void hpass_kernel(HArgs a) {
       }
 #pragma unroll
       for (int k = 0; k < SEG; ++k) {
-        const bool in = k < len;
-        const int x = x0 + k;
         if (k > 0) {
           const int slot = (k - 1) % NW;
-          const uint32_t cn = colsum<R, LPS>(LP, TP, lay.nLP, lay.nTP, x + R, dloc);
+          const uint32_t cn = colsum<R, LPS>(LP, TP, lay.nLP, lay.nTP, x0 + k + R, dloc);
           S = S + cn - ring[slot];
           ring[slot] = cn;
         }
-        c[k] = zncc_cost_from(S, LS[x], LI[x], TS[x + LPS - 1 - dloc], TI[x + LPS - 1 - dloc], N);
+        c[k] = __uint_as_float(S);
+        if (k % 2 == 1) {
+          pin(S);
+          fence();
+        }
+      }
+      fence();
+#pragma unroll
+      for (int k = 0; k < SEG; ++k) {
+        const bool in = k < len;
+        const int x = x0 + k;
+        c[k] = zncc_cost_from(__float_as_uint(c[k]), LS[x], LI[x], TS[x + LPS - 1 - dloc], TI[x + LPS - 1 - dloc], N);
         const float w = wp[k];
         ell = in ? fmaf(w, ell, c[k]) : ell;
         P = in ? P * w : P;
-        if (k % 2 == 1) {
-          pin(ell, P, S);
+        if (k % 4 == 3) {
+          pin(ell, P);
           fence();
         }
       }
@@ -553,8 +606,7 @@ __global__ __launch_bounds__(1024) void hpass_kernel(HArgs a) {
     EX[seg * LPS + dloc] = ell;
     EXS[seg] = P;
     __syncthreads();
-    float carry = 0.0f;
-    for (int s = 0; s < seg; ++s) carry = fmaf(EXS[s], carry, EX[s * LPS + dloc]);
+    const float carry = carry_in<false>(EX, EXS, seg, a.nseg, LPS, dloc, min(wave * SPW + SPW - 1, a.nseg - 1));
     reload_fence();
     // ---- loop B: exact L pass from the true carry; accumulate the carry-free R value at x0
     float prev = carry, acc = 0.0f, pi = 1.0f;
@@ -573,8 +625,7 @@ __global__ __launch_bounds__(1024) void hpass_kernel(HArgs a) {
     EX2[seg * LPS + dloc] = acc;
     EXS2[seg] = Q;
     __syncthreads();
-    float kappa = 0.0f;
-    for (int s = a.nseg - 1; s > seg; --s) kappa = fmaf(EXS2[s], kappa, EX2[s * LPS + dloc]);
+    const float kappa = carry_in<true>(EX2, EXS2, seg, a.nseg, LPS, dloc, max(a.nseg - 1 - wave * SPW, 0));
     reload_fence();
     // ---- loop D: exact R pass from the true carry, then store
     float next = kappa;
@@ -708,7 +759,7 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs a) {
   __syncthreads();
   float prev[DPL];
 #pragma unroll
-  for (int j = 0; j < DPL; ++j) {
+  for (int j = 0; j < DPL; ++j) {  // at most 15 segments: a plain serial composition
     float carry = 0.0f;
     for (int s = 0; s < wave; ++s) carry = fmaf(EXS[s], carry, EX[(s * DPL + j) * kWave + lane]);
     prev[j] = carry;
@@ -820,8 +871,8 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs a) {
 }
 
 // Combine per-chunk minima (chunks in increasing d; strict < keeps the lowest d).
-static __global__ void wta_combine_kernel(const float* part_val, const int32_t* part_idx, int nchunks, int npix,
-                                          int32_t* disp) {
+[[maybe_unused]] static __global__ void wta_combine_kernel(const float* part_val, const int32_t* part_idx,
+                                                           int nchunks, int npix, int32_t* disp) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npix) return;
   float best = part_val[p];

@@ -19,8 +19,15 @@ struct ProfRec {
 bool prof_begin(ProfRec& rec, hipStream_t s);
 void prof_end(ProfRec& rec, hipStream_t s);
 
+// Every kernel keeps its working set in registers and LDS; one that needs
+// more per-lane scratch than this is refused with ZDT_EUNSUPPORTED (checked
+// once per kernel) rather than launched.
+constexpr int kMaxScratchBytes = 1024;
+int check_kernel(const void* kernel, const char* name);
+
 template <typename Kernel, typename... A>
 int launch(const char* name, Kernel kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, A... args) {
+  if (const int rc = check_kernel((const void*)kernel, name)) return rc;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return fail(ZDT_EHIP, "%s: cannot reserve %zu B of LDS: %s", name, lds, hipGetErrorString(e));

@@ -10,8 +10,9 @@ namespace inst {
 
 template <int R, int SEG, int LPS, typename T, int MODE>
 int run_h(const HArgs& a, hipStream_t s) {
-  const HLayout lay = h_layout(a.W, R, LPS, SEG, MODE != kHPair, MODE == kCostHPair || MODE == kHPair,
-                              std::is_same<T, f16x>::value);
+  constexpr bool kDT = MODE == kCostHPair || MODE == kHPair;
+  const int wl = kDT ? (kWave / LPS) * kMaxWaves * SEG : a.W;  // as in hpass_kernel
+  const HLayout lay = h_layout(wl, R, LPS, SEG, MODE != kHPair, kDT, std::is_same<T, f16x>::value);
   static const char* const names[] = {"zncc_sums", "zncc_cost", "zncc_hpair", "dt_hpair"};
   const int spw = kWave / LPS;
   const int nw = (a.nseg + spw - 1) / spw;

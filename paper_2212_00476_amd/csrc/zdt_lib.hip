@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -29,7 +30,27 @@ std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<ProfRec> g_prof_pending;
 std::vector<std::pair<std::string, ProfAcc>> g_prof_acc;
+std::mutex g_kernel_mu;
+std::unordered_map<const void*, int> g_kernel_ok;  // kernel -> ZDT_OK or a ZDT_E* code
 }  // namespace
+
+int check_kernel(const void* kernel, const char* name) {
+  std::lock_guard<std::mutex> lk(g_kernel_mu);
+  auto it = g_kernel_ok.find(kernel);
+  if (it != g_kernel_ok.end()) {
+    if (it->second != ZDT_OK) fail(it->second, "%s: kernel was refused (per-lane scratch too large)", name);
+    return it->second;
+  }
+  hipFuncAttributes attr{};
+  const hipError_t e = hipFuncGetAttributes(&attr, kernel);
+  if (e != hipSuccess) return fail(ZDT_EHIP, "%s: hipFuncGetAttributes: %s", name, hipGetErrorString(e));
+  int rc = ZDT_OK;
+  if (attr.localSizeBytes > kMaxScratchBytes)
+    rc = fail(ZDT_EUNSUPPORTED, "%s: kernel needs %zu B of scratch per lane (limit %d)", name,
+              (size_t)attr.localSizeBytes, kMaxScratchBytes);
+  g_kernel_ok.emplace(kernel, rc);
+  return rc;
+}
 
 int fail(int code, const char* fmt, ...) {
   char buf[512];

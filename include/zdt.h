@@ -108,6 +108,65 @@ int wta_disparity(const zdt_params* params, const void* cost_hwd, int32_t* disp_
 int stereo_solve(const zdt_params* params, const uint8_t* left, const uint8_t* right, int32_t* disp_hw,
                  void* vol_hwd, void* ws, void* stream);
 
+/* One pair of a batch: its parameters and caller-owned device buffers, as for
+ * stereo_solve() (vol: zdt_volume_size(&params) bytes, ws:
+ * zdt_workspace_size(&params) bytes).  Jobs of one batch must not share a
+ * volume, workspace or disparity buffer. */
+typedef struct zdt_job {
+  zdt_params params;
+  const uint8_t* left;
+  const uint8_t* right;
+  int32_t* disp;
+  void* vol;
+  void* ws;
+} zdt_job;
+
+/* stereo_solve() for n pairs of mixed shapes on one stream, with the same
+ * results as n separate calls.  Jobs with identical parameters share every
+ * launch: each stage (cost + L/R pair, U/D pair, ...) runs as one grid over up
+ * to 32 of them, so small pairs fill the GPU together.  (The paper solves one
+ * pair at a time; its nearest analogue is the per-shape launch-configuration
+ * sweep of Sec. V-B.)  All jobs are validated before anything is enqueued;
+ * job i's error is reported with its index.  n = 0 does nothing. */
+int stereo_solve_batch(const zdt_job* jobs, int32_t n, void* stream);
+
+/* Tile plan of the register-resident passes for one shape:
+ *   h_lanes  lanes per horizontal segment: 32 (two segments per wave; the row
+ *            must split into an even number <= 32 of segments of exactly
+ *            h_seg values) or 64 (up to 16 segments of at most h_seg values)
+ *   h_seg    compiled horizontal segment length: 8, 20, 40, 60 (32 lanes) or
+ *            16, 40, 80 (64 lanes)
+ *   v_seg    compiled vertical segment length: 8, 12, 24, 48, 72 (one wave per
+ *            segment, up to 16 per column)
+ * A plan changes only how rows and columns are cut into register-resident
+ * segments; results agree with every other plan up to float32 rounding of the
+ * segment-carry composition. */
+typedef struct zdt_plan {
+  int32_t h_lanes, h_seg, v_seg;
+  int32_t reserved; /* zero */
+} zdt_plan;
+
+/* Every plan that fits params' shape, the default first: writes up to `max` of
+ * them to `out` (HOST array) and returns how many there are (< 0: error). */
+int zdt_plan_candidates(const zdt_params* params, zdt_plan* out, int max);
+
+/* The plan used for params' shape (W, H, D, r, vol_dtype): the one pinned by
+ * zdt_set_plan() or zdt_autotune(), else the default. */
+int zdt_get_plan(const zdt_params* params, zdt_plan* out);
+
+/* Pin `plan` (a candidate for the shape, else ZDT_EINVAL) for every later call
+ * on params' shape in this process; NULL returns the shape to its default.
+ * Thread-safe; calls already enqueued keep the plan they were issued with. */
+int zdt_set_plan(const zdt_params* params, const zdt_plan* plan);
+
+/* Autotuner: if `cache_path` (may be NULL) holds a plan for the shape, pin it;
+ * otherwise time stereo_solve() under every candidate plan on `stream` (two
+ * warm-up and five timed runs each, on a synthetic pair in buffers it
+ * allocates and frees), pin the fastest and append it to `cache_path`.  The
+ * chosen plan is written to *chosen when that is not NULL.  Synchronises the
+ * stream; not for use under stream capture. */
+int zdt_autotune(const zdt_params* params, const char* cache_path, zdt_plan* chosen, void* stream);
+
 /* Exact integer sums behind the cost (Sec. IV-B summation and the Pi_RT term
  * of Eq. OP_ZNCC), exposed for verification; any output pointer may be NULL:
  *   s_l, s_ll      [H][W]        sum of I_R and I_R^2 over the window at (x,y)

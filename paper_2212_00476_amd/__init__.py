@@ -12,11 +12,13 @@ the tests and the benchmark.  PyTorch provides device memory and streams only.
 from __future__ import annotations
 
 from ._lib import (ZDT_BF16, ZDT_F16, ZDT_F32, ZDT_FLAG_GUIDE_TARGET, ZDT_FLAG_NORMALIZE, ZdtError, ZdtParams,
-                   dt_aggregate, load, params, profile_collect, profile_enable, stereo_solve, volume_size,
-                   workspace_size, wta_disparity, zncc_cost_volume, zncc_window_sums)
+                   autotune, dt_aggregate, get_plan, load, params, plan_candidates, profile_collect, profile_enable,
+                   set_plan, stereo_solve, stereo_solve_batch, volume_size, workspace_size, wta_disparity,
+                   zncc_cost_volume, zncc_window_sums)
 
 __all__ = ["ZDT_F32", "ZDT_F16", "ZDT_BF16", "ZDT_FLAG_NORMALIZE", "ZDT_FLAG_GUIDE_TARGET", "ZdtError", "ZdtParams",
-           "params", "load", "zncc_cost_volume", "dt_aggregate", "wta_disparity", "stereo_solve", "zncc_window_sums",
+           "params", "load", "zncc_cost_volume", "dt_aggregate", "wta_disparity", "stereo_solve",
+           "stereo_solve_batch", "plan_candidates", "get_plan", "set_plan", "autotune", "zncc_window_sums",
            "workspace_size", "volume_size", "profile_enable", "profile_collect", "torch_dtype", "Solver"]
 
 

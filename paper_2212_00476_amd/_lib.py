@@ -19,7 +19,8 @@ ZDT_FLAG_NORMALIZE = 1
 ZDT_FLAG_GUIDE_TARGET = 2
 
 EXPORTED = ("zdt_workspace_size", "zdt_volume_size", "zncc_cost_volume", "dt_aggregate", "wta_disparity",
-            "stereo_solve", "zncc_window_sums", "zdt_last_error", "zdt_profile_enable", "zdt_profile_collect",
+            "stereo_solve", "stereo_solve_batch", "zdt_plan_candidates", "zdt_get_plan", "zdt_set_plan",
+            "zdt_autotune", "zncc_window_sums", "zdt_last_error", "zdt_profile_enable", "zdt_profile_collect",
             "zdt_profile_entry")
 
 
@@ -28,6 +29,19 @@ class ZdtParams(ctypes.Structure):
                 ("max_disp", ctypes.c_int32), ("radius", ctypes.c_int32), ("sigma_s", ctypes.c_float),
                 ("sigma_r", ctypes.c_float), ("dt_iters", ctypes.c_int32), ("vol_dtype", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+
+
+class ZdtJob(ctypes.Structure):
+    _fields_ = [("params", ZdtParams), ("left", ctypes.c_void_p), ("right", ctypes.c_void_p),
+                ("disp", ctypes.c_void_p), ("vol", ctypes.c_void_p), ("ws", ctypes.c_void_p)]
+
+
+class ZdtPlan(ctypes.Structure):
+    _fields_ = [("h_lanes", ctypes.c_int32), ("h_seg", ctypes.c_int32), ("v_seg", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def astuple(self):
+        return (self.h_lanes, self.h_seg, self.v_seg)
 
 
 class ZdtError(RuntimeError):
@@ -57,11 +71,18 @@ def load():
     lib.wta_disparity.argtypes = [PP, P, P, P]
     lib.stereo_solve.argtypes = [PP, P, P, P, P, P, P]
     lib.zncc_window_sums.argtypes = [PP, P, P, P, P, P, P, P, P]
+    lib.stereo_solve_batch.argtypes = [ctypes.POINTER(ZdtJob), ctypes.c_int32, P]
+    PL = ctypes.POINTER(ZdtPlan)
+    lib.zdt_plan_candidates.argtypes = [PP, PL, ctypes.c_int]
+    lib.zdt_get_plan.argtypes = [PP, PL]
+    lib.zdt_set_plan.argtypes = [PP, PL]
+    lib.zdt_autotune.argtypes = [PP, ctypes.c_char_p, PL, P]
     lib.zdt_last_error.restype = ctypes.c_char_p
     lib.zdt_profile_enable.argtypes = [ctypes.c_int]
     lib.zdt_profile_entry.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
-    for f in ("zncc_cost_volume", "dt_aggregate", "wta_disparity", "stereo_solve", "zncc_window_sums",
+    for f in ("zncc_cost_volume", "dt_aggregate", "wta_disparity", "stereo_solve", "stereo_solve_batch",
+              "zdt_plan_candidates", "zdt_get_plan", "zdt_set_plan", "zdt_autotune", "zncc_window_sums",
               "zdt_profile_enable", "zdt_profile_collect", "zdt_profile_entry"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
@@ -118,6 +139,44 @@ def wta_disparity(p, cost, disp, stream=None):
 def stereo_solve(p, left, right, disp, vol, ws=None, stream=None):
     _check("stereo_solve", load().stereo_solve(ctypes.byref(p), _ptr(left), _ptr(right), _ptr(disp), _ptr(vol),
                                                _ptr(ws), _stream(stream)))
+
+
+def stereo_solve_batch(jobs, stream=None):
+    """jobs: sequence of (params, left, right, disp, vol, ws) with device tensors (ws may be None)."""
+    arr = (ZdtJob * max(1, len(jobs)))()
+    for i, (p, left, right, disp, vol, ws) in enumerate(jobs):
+        arr[i] = ZdtJob(p, _ptr(left), _ptr(right), _ptr(disp), _ptr(vol), _ptr(ws))
+    _check("stereo_solve_batch", load().stereo_solve_batch(arr, len(jobs), _stream(stream)))
+
+
+def plan_candidates(p):
+    """Every tile plan (h_lanes, h_seg, v_seg) that fits the shape, the default first."""
+    lib = load()
+    n = lib.zdt_plan_candidates(ctypes.byref(p), None, 0)
+    if n < 0:
+        _check("zdt_plan_candidates", n)
+    out = (ZdtPlan * n)()
+    n = lib.zdt_plan_candidates(ctypes.byref(p), out, n)
+    return [out[i].astuple() for i in range(n)]
+
+
+def get_plan(p):
+    out = ZdtPlan()
+    _check("zdt_get_plan", load().zdt_get_plan(ctypes.byref(p), ctypes.byref(out)))
+    return out.astuple()
+
+
+def set_plan(p, plan):
+    """Pin plan = (h_lanes, h_seg, v_seg) for p's shape; None restores the default."""
+    pl = None if plan is None else ctypes.byref(ZdtPlan(*plan, 0))
+    _check("zdt_set_plan", load().zdt_set_plan(ctypes.byref(p), pl))
+
+
+def autotune(p, cache_path=None, stream=None):
+    out = ZdtPlan()
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _check("zdt_autotune", load().zdt_autotune(ctypes.byref(p), path, ctypes.byref(out), _stream(stream)))
+    return out.astuple()
 
 
 def zncc_window_sums(p, left, right, s_l=None, s_ll=None, s_t=None, s_tt=None, s_rt=None, stream=None):

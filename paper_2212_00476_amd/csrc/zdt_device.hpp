@@ -238,6 +238,21 @@ struct HArgs {
   int nchunks;     // disparity chunks of LPS lanes per row
 };
 
+// Multi-job launches: grid z indexes the job, and each job's buffers come from
+// a pointer table passed with the kernel arguments (jobs of one launch share
+// shape and parameters; a single job is a table of one).
+constexpr int kMaxJobs = 32;
+struct HJob {
+  const uint8_t* left;
+  const uint8_t* right;
+  const uint8_t* guide;
+  void* vol;
+  int8_t* ex;
+};
+struct HJobs {
+  HJob j[kMaxJobs];
+};
+
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
 // DT weight between G(a) and its predecessor G(b): exp(-1/sigma_s - |G(a)-G(b)| / (255 sigma_r)).
@@ -428,8 +443,17 @@ constexpr int h_waves_per_eu() {
 }
 
 template <int R, int SEG, int LPS, typename T, int MODE>
-__global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void hpass_kernel(HArgs a) {
+__global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void hpass_kernel(HArgs args, HJobs jobs) {
   extern __shared__ uint32_t smem[];
+  HArgs a = args;
+  {
+    const HJob& jb = jobs.j[blockIdx.z];
+    a.left = jb.left;
+    a.right = jb.right;
+    a.guide = jb.guide;
+    a.vol = jb.vol;
+    a.ex = jb.ex;
+  }
   constexpr int NW = 2 * R + 1;  // window side
   constexpr int N = NW * NW;
   constexpr int SPW = kWave / LPS;  // segments per wave
@@ -665,6 +689,18 @@ struct VArgs {
   int segl, nw;
 };
 
+struct VJob {
+  const uint8_t* guide;
+  void* vol;
+  int8_t* ex;
+  int32_t* disp;
+  float* part_val;
+  int32_t* part_idx;
+};
+struct VJobs {
+  VJob j[kMaxJobs];
+};
+
 // WV[H+1] (+ SEG spare entries), EX/EX2 [16*64*DPL], EXS/EXS2 [16], and for
 // scaled FP16 XP[2][H + SEG], the column's exponents per half-wave chunk
 __host__ __device__ inline int v_lds_words(int H, int SEG, int DPL, bool scaled) {
@@ -679,8 +715,18 @@ __device__ __forceinline__ float wave_min(float v) {
 
 // FULL: every wave's segment holds exactly SEG rows (checked by the host).
 template <int SEG, bool FULL, typename T, int DPL, bool WTA>
-__global__ __launch_bounds__(1024) void vpass_kernel(VArgs a) {
+__global__ __launch_bounds__(1024) void vpass_kernel(VArgs args, VJobs jobs) {
   extern __shared__ uint32_t smem[];
+  VArgs a = args;
+  {
+    const VJob& jb = jobs.j[blockIdx.z];
+    a.guide = jb.guide;
+    a.vol = jb.vol;
+    a.ex = jb.ex;
+    a.disp = jb.disp;
+    a.part_val = jb.part_val;
+    a.part_idx = jb.part_idx;
+  }
   constexpr bool kHalf = std::is_same<T, f16x>::value;  // exponent-scaled FP16
   static_assert(DPL == 1 || !kHalf, "FP16 exponents are per half-wave chunk");
   constexpr uint32_t kBytes = sizeof(T);
@@ -871,20 +917,28 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs a) {
 }
 
 // Combine per-chunk minima (chunks in increasing d; strict < keeps the lowest d).
-[[maybe_unused]] static __global__ void wta_combine_kernel(const float* part_val, const int32_t* part_idx,
-                                                           int nchunks, int npix, int32_t* disp) {
+struct WJob {
+  const float* part_val;
+  const int32_t* part_idx;
+  int32_t* disp;
+};
+struct WJobs {
+  WJob j[kMaxJobs];
+};
+[[maybe_unused]] static __global__ void wta_combine_kernel(WJobs jobs, int nchunks, int npix) {
+  const WJob& jb = jobs.j[blockIdx.z];
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npix) return;
-  float best = part_val[p];
-  int idx = part_idx[p];
+  float best = jb.part_val[p];
+  int idx = jb.part_idx[p];
   for (int c = 1; c < nchunks; ++c) {
-    const float v = part_val[(size_t)c * npix + p];
+    const float v = jb.part_val[(size_t)c * npix + p];
     if (v < best) {
       best = v;
-      idx = part_idx[(size_t)c * npix + p];
+      idx = jb.part_idx[(size_t)c * npix + p];
     }
   }
-  disp[p] = idx;
+  jb.disp[p] = idx;
 }
 
 // Standalone WTA: each wave takes pixels p = global wave id, + total waves, ...

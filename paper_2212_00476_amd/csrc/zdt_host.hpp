@@ -56,15 +56,13 @@ inline int h_full_seg32(int W) {
     if (W % seg == 0 && (W / seg) % 2 == 0 && W / seg <= 2 * kMaxWaves) return seg;
   return 0;
 }
-inline int h_lps(int dtype, int mode, int W) {
-  (void)dtype;
-  return ((mode == kCostHPair || mode == kHPair) && h_full_seg32(W)) ? 32 : 64;
-}
 
 // Kernel dispatch, one set per volume element type (defined in zdt_inst_*.hip).
-#define ZDT_DECLARE_DISPATCH(SUFFIX)                                                                      \
-  int dispatch_h_##SUFFIX(int mode, int R, int seg, int lps, const HArgs& a, hipStream_t s);            \
-  int dispatch_v_##SUFFIX(int seg, int dpl, bool wta, const VArgs& a, int nchunks, hipStream_t s);     \
+#define ZDT_DECLARE_DISPATCH(SUFFIX)                                                                           \
+  int dispatch_h_##SUFFIX(int mode, int R, int seg, int lps, const HArgs& a, const HJobs& jobs, int n,        \
+                          hipStream_t s);                                                                     \
+  int dispatch_v_##SUFFIX(int seg, int dpl, bool wta, const VArgs& a, const VJobs& jobs, int n, int nchunks,   \
+                          hipStream_t s);                                                                     \
   int dispatch_wta_##SUFFIX(const void* vol, int npix, int D, int32_t* disp, hipStream_t s);
 ZDT_DECLARE_DISPATCH(f32)
 ZDT_DECLARE_DISPATCH(f16)

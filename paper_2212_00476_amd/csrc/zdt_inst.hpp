@@ -9,7 +9,7 @@ namespace zdt {
 namespace inst {
 
 template <int R, int SEG, int LPS, typename T, int MODE>
-int run_h(const HArgs& a, hipStream_t s) {
+int run_h(const HArgs& a, const HJobs& jobs, int n, hipStream_t s) {
   constexpr bool kDT = MODE == kCostHPair || MODE == kHPair;
   const int wl = kDT ? (kWave / LPS) * kMaxWaves * SEG : a.W;  // as in hpass_kernel
   const HLayout lay = h_layout(wl, R, LPS, SEG, MODE != kHPair, kDT, std::is_same<T, f16x>::value);
@@ -18,29 +18,30 @@ int run_h(const HArgs& a, hipStream_t s) {
   const int nw = (a.nseg + spw - 1) / spw;
   HArgs b = a;
   b.nchunks = (a.D + LPS - 1) / LPS;
-  dim3 grid(b.nchunks, a.H);
+  dim3 grid(b.nchunks, a.H, n);
   if constexpr ((MODE == kCostHPair || MODE == kHPair) && sizeof(T) == 2) {
-    // 1-D grid with the chunk pairs of a row on one XCD (see h_tile)
+    // 1-D grid (per job) with the chunk pairs of a row on one XCD (see h_tile)
     const int items = a.H * ((b.nchunks + 1) / 2);
-    grid = dim3((unsigned)((items + 7) / 8 * 16));
+    grid = dim3((unsigned)((items + 7) / 8 * 16), 1, n);
   }
-  return launch(names[MODE], hpass_kernel<R, SEG, LPS, T, MODE>, grid, dim3(kWave * nw), (size_t)lay.words * 4, s, b);
+  return launch(names[MODE], hpass_kernel<R, SEG, LPS, T, MODE>, grid, dim3(kWave * nw), (size_t)lay.words * 4, s, b,
+                jobs);
 }
 
 template <int R, int LPS, typename T, int MODE>
-int run_h_seg(int seg, const HArgs& a, hipStream_t s) {
+int run_h_seg(int seg, const HArgs& a, const HJobs& jobs, int n, hipStream_t s) {
   if constexpr (LPS == 32) {
     switch (seg) {
-      case 8: return run_h<R, 8, LPS, T, MODE>(a, s);
-      case 20: return run_h<R, 20, LPS, T, MODE>(a, s);
-      case 40: return run_h<R, 40, LPS, T, MODE>(a, s);
-      case 60: return run_h<R, 60, LPS, T, MODE>(a, s);
+      case 8: return run_h<R, 8, LPS, T, MODE>(a, jobs, n, s);
+      case 20: return run_h<R, 20, LPS, T, MODE>(a, jobs, n, s);
+      case 40: return run_h<R, 40, LPS, T, MODE>(a, jobs, n, s);
+      case 60: return run_h<R, 60, LPS, T, MODE>(a, jobs, n, s);
     }
   } else {
     switch (seg) {
-      case 16: return run_h<R, 16, LPS, T, MODE>(a, s);
-      case 40: return run_h<R, 40, LPS, T, MODE>(a, s);
-      case 80: return run_h<R, 80, LPS, T, MODE>(a, s);
+      case 16: return run_h<R, 16, LPS, T, MODE>(a, jobs, n, s);
+      case 40: return run_h<R, 40, LPS, T, MODE>(a, jobs, n, s);
+      case 80: return run_h<R, 80, LPS, T, MODE>(a, jobs, n, s);
     }
   }
   return fail(ZDT_EUNSUPPORTED, "no H-pass instance for segment length %d", seg);
@@ -48,13 +49,13 @@ int run_h_seg(int seg, const HArgs& a, hipStream_t s) {
 
 // Streaming modes (sums, raw cost) keep no per-segment registers: SEG = 0.
 template <typename T, int MODE, int LPS>
-int run_h_radius(int R, int seg, const HArgs& a, hipStream_t s) {
+int run_h_radius(int R, int seg, const HArgs& a, const HJobs& jobs, int n, hipStream_t s) {
   constexpr bool stream = MODE == kSums || MODE == kCost;
   switch (R) {
 #define ZDT_CASE(RR)                                                \
   case RR:                                                          \
-    if constexpr (stream) return run_h<RR, 0, 64, T, MODE>(a, s);   \
-    else return run_h_seg<RR, LPS, T, MODE>(seg, a, s);
+    if constexpr (stream) return run_h<RR, 0, 64, T, MODE>(a, jobs, n, s); \
+    else return run_h_seg<RR, LPS, T, MODE>(seg, a, jobs, n, s);
     ZDT_CASE(0) ZDT_CASE(1) ZDT_CASE(2) ZDT_CASE(3) ZDT_CASE(4) ZDT_CASE(5) ZDT_CASE(6)
 #undef ZDT_CASE
   }
@@ -62,16 +63,18 @@ int run_h_radius(int R, int seg, const HArgs& a, hipStream_t s) {
 }
 
 template <int SEG, bool FULL, typename T, int DPL, bool WTA>
-int run_v(const VArgs& a, int nchunks, hipStream_t s) {
-  return launch(WTA ? "dt_vpair_wta" : "dt_vpair", vpass_kernel<SEG, FULL, T, DPL, WTA>, dim3(nchunks, a.W),
-                dim3(kWave * a.nw), (size_t)v_lds_words(a.H, SEG, DPL, std::is_same<T, f16x>::value) * 4, s, a);
+int run_v(const VArgs& a, const VJobs& jobs, int n, int nchunks, hipStream_t s) {
+  return launch(WTA ? "dt_vpair_wta" : "dt_vpair", vpass_kernel<SEG, FULL, T, DPL, WTA>, dim3(nchunks, a.W, n),
+                dim3(kWave * a.nw), (size_t)v_lds_words(a.H, SEG, DPL, std::is_same<T, f16x>::value) * 4, s, a, jobs);
 }
 
 template <typename T, int DPL, bool WTA>
-int run_v_seg(int seg, bool full, const VArgs& a, int nchunks, hipStream_t s) {
+int run_v_seg(int seg, bool full, const VArgs& a, const VJobs& jobs, int n, int nchunks, hipStream_t s) {
   switch (seg) {
-#define ZDT_CASE(SS) \
-  case SS: return full ? run_v<SS, true, T, DPL, WTA>(a, nchunks, s) : run_v<SS, false, T, DPL, WTA>(a, nchunks, s);
+#define ZDT_CASE(SS)                                                       \
+  case SS:                                                                 \
+    return full ? run_v<SS, true, T, DPL, WTA>(a, jobs, n, nchunks, s)     \
+                : run_v<SS, false, T, DPL, WTA>(a, jobs, n, nchunks, s);
     ZDT_CASE(8) ZDT_CASE(12) ZDT_CASE(24) ZDT_CASE(48) ZDT_CASE(72)
 #undef ZDT_CASE
   }
@@ -86,35 +89,37 @@ int run_v_seg(int seg, bool full, const VArgs& a, int nchunks, hipStream_t s) {
 
 namespace zdt {
 
-int ZDT_CAT(dispatch_h_, ZDT_SUFFIX)(int mode, int R, int seg, int lps, const HArgs& a, hipStream_t s) {
+int ZDT_CAT(dispatch_h_, ZDT_SUFFIX)(int mode, int R, int seg, int lps, const HArgs& a, const HJobs& jobs, int n,
+                                     hipStream_t s) {
   using T = ZDT_ELEM;
   constexpr bool f32 = std::is_same<T, float>::value;
   constexpr bool f16x_ = std::is_same<T, f16x>::value;
   switch (mode) {
     case kCost:
-      if constexpr (!f16x_) return inst::run_h_radius<T, kCost, 64>(R, seg, a, s);
+      if constexpr (!f16x_) return inst::run_h_radius<T, kCost, 64>(R, seg, a, jobs, n, s);
       break;
     case kCostHPair:
-      if (lps == 32) return inst::run_h_radius<T, kCostHPair, 32>(R, seg, a, s);
-      if (lps == 64) return inst::run_h_radius<T, kCostHPair, 64>(R, seg, a, s);
+      if (lps == 32) return inst::run_h_radius<T, kCostHPair, 32>(R, seg, a, jobs, n, s);
+      if (lps == 64) return inst::run_h_radius<T, kCostHPair, 64>(R, seg, a, jobs, n, s);
       break;
     case kHPair:
-      if (lps == 32) return inst::run_h_seg<0, 32, T, kHPair>(seg, a, s);
-      if (lps == 64) return inst::run_h_seg<0, 64, T, kHPair>(seg, a, s);
+      if (lps == 32) return inst::run_h_seg<0, 32, T, kHPair>(seg, a, jobs, n, s);
+      if (lps == 64) return inst::run_h_seg<0, 64, T, kHPair>(seg, a, jobs, n, s);
       break;
     case kSums:
-      if constexpr (f32) return inst::run_h_radius<T, kSums, 64>(R, seg, a, s);
+      if constexpr (f32) return inst::run_h_radius<T, kSums, 64>(R, seg, a, jobs, n, s);
       break;
   }
   return fail(ZDT_EUNSUPPORTED, "no H-pass instance for mode %d, %d lanes per segment", mode, lps);
 }
 
-int ZDT_CAT(dispatch_v_, ZDT_SUFFIX)(int seg, int dpl, bool wta, const VArgs& a, int nchunks, hipStream_t s) {
+int ZDT_CAT(dispatch_v_, ZDT_SUFFIX)(int seg, int dpl, bool wta, const VArgs& a, const VJobs& jobs, int n,
+                                     int nchunks, hipStream_t s) {
   using T = ZDT_ELEM;
   if (dpl != 1) return fail(ZDT_EUNSUPPORTED, "V pass with %d disparities per lane", dpl);
   const bool full = a.segl == seg && a.nw * seg == a.H;
-  if (!wta) return inst::run_v_seg<T, 1, false>(seg, full, a, nchunks, s);
-  return inst::run_v_seg<T, 1, true>(seg, full, a, nchunks, s);
+  if (!wta) return inst::run_v_seg<T, 1, false>(seg, full, a, jobs, n, nchunks, s);
+  return inst::run_v_seg<T, 1, true>(seg, full, a, jobs, n, nchunks, s);
 }
 
 int ZDT_CAT(dispatch_wta_, ZDT_SUFFIX)(const void* vol, int npix, int D, int32_t* disp, hipStream_t s) {

@@ -7,8 +7,12 @@
 
 #include <cmath>
 #include <cstdarg>
+#include <algorithm>
 #include <cstdio>
+#include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <unordered_map>
 #include <utility>
@@ -119,34 +123,118 @@ int check_params(const zdt_params* p, const char* who) {
   return ZDT_OK;
 }
 
-// A line of n values split into nseg <= maxseg segments of segl <= seg values
-// (the smallest compiled seg that fits).
+// A line of n values split into segments of at most `seg` values: ceil(n/seg)
+// segments of equal length segl (the last one shorter).
 struct Split {
   int seg, segl, nseg;
 };
 
+Split split_with(int n, int seg) {
+  const int n0 = (n + seg - 1) / seg;
+  const int segl = (n + n0 - 1) / n0;
+  return {seg, segl, (n + segl - 1) / segl};
+}
+
+// The smallest compiled segment length that splits n into <= maxseg segments.
 Split split_line(int n, const int* segs, int nsegs, int maxseg) {
   for (int i = 0; i < nsegs; ++i)
-    if (n <= maxseg * segs[i]) {
-      const int n0 = (n + segs[i] - 1) / segs[i];
-      const int segl = (n + n0 - 1) / n0;
-      return {segs[i], segl, (n + segl - 1) / segl};
-    }
+    if (n <= maxseg * segs[i]) return split_with(n, segs[i]);
   return {0, 0, 0};
 }
 
-Split h_split(const zdt_params* p, int lps, int mode) {
-  if (mode == kSums || mode == kCost) {  // streamed: any segment length, 16 waves
-    const int segl = (p->width + kMaxWaves - 1) / kMaxWaves;
-    return {0, segl, (p->width + segl - 1) / segl};
-  }
-  if (lps == 32) {
-    const int seg = h_full_seg32(p->width);
-    return {seg, seg, p->width / seg};
-  }
-  return split_line(p->width, kHSegs64, kNumHSegs64, kMaxWaves);
+// Streamed H modes (sums, raw cost) take any segment length with 16 waves.
+Split h_split_stream(const zdt_params* p) {
+  const int segl = (p->width + kMaxWaves - 1) / kMaxWaves;
+  return {0, segl, (p->width + segl - 1) / segl};
 }
-Split v_split(const zdt_params* p) { return split_line(p->height, kVSegs, kNumVSegs, kMaxWaves); }
+
+// ---- tile plans of the register-resident passes (zdt_plan in zdt.h)
+struct Plan {
+  int h_lanes, h_seg, v_seg;
+};
+
+bool in_list(int v, const int* list, int n) {
+  for (int i = 0; i < n; ++i)
+    if (list[i] == v) return true;
+  return false;
+}
+
+bool h_plan_ok(int W, int lanes, int seg) {
+  if (lanes == 32)
+    return in_list(seg, kHSegs32, 4) && W % seg == 0 && (W / seg) % 2 == 0 && W / seg <= 2 * kMaxWaves;
+  if (lanes == 64) return in_list(seg, kHSegs64, kNumHSegs64) && (W + seg - 1) / seg <= kMaxWaves;
+  return false;
+}
+
+bool v_plan_ok(int H, int seg) { return in_list(seg, kVSegs, kNumVSegs) && (H + seg - 1) / seg <= kMaxWaves; }
+
+Split h_split_plan(int W, const Plan& pl) {
+  if (pl.h_lanes == 32) return {pl.h_seg, pl.h_seg, W / pl.h_seg};
+  return split_with(W, pl.h_seg);
+}
+
+Split v_split_plan(int H, const Plan& pl) { return split_with(H, pl.v_seg); }
+
+// Default plan: two 32-lane segments per wave when the row splits into an even
+// number of full segments, else 64-lane segments; the shortest V segments
+// that cover the column with 16 waves.
+Plan default_plan(const zdt_params* p) {
+  Plan pl{};
+  if (const int s32 = h_full_seg32(p->width)) {
+    pl.h_lanes = 32;
+    pl.h_seg = s32;
+  } else {
+    pl.h_lanes = 64;
+    pl.h_seg = split_line(p->width, kHSegs64, kNumHSegs64, kMaxWaves).seg;
+  }
+  pl.v_seg = split_line(p->height, kVSegs, kNumVSegs, kMaxWaves).seg;
+  return pl;
+}
+
+// Every valid plan for the shape, the default first; H and V options that give
+// the same split as a shorter compiled length are left out.
+std::vector<Plan> plan_candidates(const zdt_params* p) {
+  const int W = p->width, H = p->height;
+  std::vector<std::pair<int, int>> hs;
+  for (int seg : kHSegs32)
+    if (h_plan_ok(W, 32, seg)) hs.push_back({32, seg});
+  int last = -1;
+  for (int seg : kHSegs64) {
+    const int n0 = (W + seg - 1) / seg;
+    if (h_plan_ok(W, 64, seg) && n0 != last) hs.push_back({64, seg});
+    last = n0;
+  }
+  std::vector<int> vs;
+  last = -1;
+  for (int seg : kVSegs) {
+    const int n0 = (H + seg - 1) / seg;
+    if (v_plan_ok(H, seg) && n0 != last) vs.push_back(seg);
+    last = n0;
+  }
+  const Plan d = default_plan(p);
+  std::vector<Plan> out{d};
+  for (auto& h : hs)
+    for (int v : vs)
+      if (!(h.first == d.h_lanes && h.second == d.h_seg && v == d.v_seg)) out.push_back({h.first, h.second, v});
+  return out;
+}
+
+struct PlanKey {
+  int W, H, D, R, dtype;
+  bool operator<(const PlanKey& o) const {
+    return std::tie(W, H, D, R, dtype) < std::tie(o.W, o.H, o.D, o.R, o.dtype);
+  }
+};
+PlanKey plan_key(const zdt_params* p) { return {p->width, p->height, p->max_disp, p->radius, p->vol_dtype}; }
+
+std::mutex g_plan_mu;
+std::map<PlanKey, Plan> g_plans;  // plans pinned by zdt_set_plan / zdt_autotune
+
+Plan plan_for(const zdt_params* p) {
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  auto it = g_plans.find(plan_key(p));
+  return it != g_plans.end() ? it->second : default_plan(p);
+}
 
 bool normalized(const zdt_params* p) { return (p->flags & ZDT_FLAG_NORMALIZE) || p->vol_dtype != ZDT_F32; }
 
@@ -166,12 +254,9 @@ double total_scale(const zdt_params* p) {
 
 float range_coef(const zdt_params* p) { return std::isinf(p->sigma_r) ? 0.0f : 1.0f / (255.0f * p->sigma_r); }
 
-HArgs make_hargs(const zdt_params* p, const uint8_t* left, const uint8_t* right, const uint8_t* guide, void* vol,
-                 float out_scale, const Split& sp) {
+// Arguments shared by all jobs of a launch (pointers come from the job table).
+HArgs make_hargs(const zdt_params* p, float out_scale) {
   HArgs a{};
-  a.left = left;
-  a.right = right;
-  a.guide = guide;
   a.pitch = p->pitch;
   a.W = p->width;
   a.H = p->height;
@@ -179,60 +264,60 @@ HArgs make_hargs(const zdt_params* p, const uint8_t* left, const uint8_t* right,
   a.inv_sigma_s = 1.0f / p->sigma_s;
   a.range_coef = range_coef(p);
   a.out_scale = out_scale;
-  a.vol = vol;
+  return a;
+}
+
+VArgs make_vargs(const zdt_params* p, float out_scale) {
+  VArgs a{};
+  a.pitch = p->pitch;
+  a.W = p->width;
+  a.H = p->height;
+  a.D = p->max_disp;
+  a.inv_sigma_s = 1.0f / p->sigma_s;
+  a.range_coef = range_coef(p);
+  a.out_scale = out_scale;
+  return a;
+}
+
+// Launch an H-pass mode for n jobs.  `scaled` selects the exponent-scaled FP16
+// working volume (tables carry the exponent maps).
+int launch_h(const zdt_params* p, int dtype, int mode, bool scaled, HArgs a, const HJobs& t, int n, const Plan& pl,
+             hipStream_t s) {
+  int lps;
+  Split sp;
+  if (mode == kSums || mode == kCost) {
+    lps = 64;
+    sp = h_split_stream(p);
+  } else {
+    lps = pl.h_lanes;
+    sp = h_split_plan(p->width, pl);
+  }
   a.segl = sp.segl;
   a.nseg = sp.nseg;
-  return a;
-}
-
-VArgs make_vargs(const zdt_params* p, const uint8_t* guide, void* vol, float out_scale, const Split& sp) {
-  VArgs a{};
-  a.guide = guide;
-  a.pitch = p->pitch;
-  a.W = p->width;
-  a.H = p->height;
-  a.D = p->max_disp;
-  a.inv_sigma_s = 1.0f / p->sigma_s;
-  a.range_coef = range_coef(p);
-  a.out_scale = out_scale;
-  a.vol = vol;
-  a.segl = sp.segl;
-  a.nw = sp.nseg;
-  return a;
-}
-
-// Launch an H-pass mode: the lane layout follows the volume type and mode.
-int run_h_mode(const zdt_params* p, int dtype, int mode, const uint8_t* left, const uint8_t* right,
-               const uint8_t* guide, void* vol, float scale, int8_t* ex, hipStream_t s, HArgs* extra = nullptr) {
-  const int lps = h_lps(dtype, mode, p->width);
-  const Split sp = h_split(p, lps, mode);
-  HArgs a = make_hargs(p, left, right, guide, vol, scale, sp);
-  a.ex = ex;
-  if (extra) {
-    a.s_rt = extra->s_rt;
-    a.s_l = extra->s_l;
-    a.s_ll = extra->s_ll;
-    a.s_t = extra->s_t;
-    a.s_tt = extra->s_tt;
-  }
   const int R = mode == kHPair ? 0 : p->radius;
   switch (dtype) {
-    case ZDT_F32: return dispatch_h_f32(mode, R, sp.seg, lps, a, s);
+    case ZDT_F32: return dispatch_h_f32(mode, R, sp.seg, lps, a, t, n, s);
     case ZDT_F16:
-      return ex ? dispatch_h_f16x(mode, R, sp.seg, lps, a, s) : dispatch_h_f16(mode, R, sp.seg, lps, a, s);
-    case ZDT_BF16: return dispatch_h_bf16(mode, R, sp.seg, lps, a, s);
+      return scaled ? dispatch_h_f16x(mode, R, sp.seg, lps, a, t, n, s) : dispatch_h_f16(mode, R, sp.seg, lps, a, t, n, s);
+    case ZDT_BF16: return dispatch_h_bf16(mode, R, sp.seg, lps, a, t, n, s);
   }
   return fail(ZDT_EINVAL, "bad dtype %d", dtype);
 }
 
-int dispatch_v(int dtype, int seg, int dpl, bool wta, const VArgs& a, int nchunks, hipStream_t s) {
-  switch (dtype) {
-    case ZDT_F32: return dispatch_v_f32(seg, dpl, wta, a, nchunks, s);
+int launch_v(const zdt_params* p, bool scaled, bool wta, VArgs a, const VJobs& t, int n, const Plan& pl,
+             hipStream_t s) {
+  const Split sp = v_split_plan(p->height, pl);
+  a.segl = sp.segl;
+  a.nw = sp.nseg;
+  const int nchunks = (p->max_disp + kWave - 1) / kWave;
+  switch (p->vol_dtype) {
+    case ZDT_F32: return dispatch_v_f32(sp.seg, 1, wta, a, t, n, nchunks, s);
     case ZDT_F16:
-      return a.ex ? dispatch_v_f16x(seg, dpl, wta, a, nchunks, s) : dispatch_v_f16(seg, dpl, wta, a, nchunks, s);
-    case ZDT_BF16: return dispatch_v_bf16(seg, dpl, wta, a, nchunks, s);
+      return scaled ? dispatch_v_f16x(sp.seg, 1, wta, a, t, n, nchunks, s)
+                    : dispatch_v_f16(sp.seg, 1, wta, a, t, n, nchunks, s);
+    case ZDT_BF16: return dispatch_v_bf16(sp.seg, 1, wta, a, t, n, nchunks, s);
   }
-  return fail(ZDT_EINVAL, "bad dtype %d", dtype);
+  return fail(ZDT_EINVAL, "bad dtype %d", p->vol_dtype);
 }
 
 int dispatch_wta(int dtype, const void* vol, int npix, int D, int32_t* disp, hipStream_t s) {
@@ -244,23 +329,13 @@ int dispatch_wta(int dtype, const void* vol, int npix, int D, int32_t* disp, hip
   return fail(ZDT_EINVAL, "bad dtype %d", dtype);
 }
 
-// Shape of the WTA-fused V pass: DPL disparities per lane and the number of
-// disparity chunks (several chunks need the partial-minimum workspace).
-struct VWta {
-  int dpl, nchunks;
-};
-VWta v_wta_shape(const zdt_params* p, int seg) {
-  (void)seg;
-  // one disparity per lane keeps the kernel at two workgroups per CU; several
-  // 64-disparity chunks are combined by a small second kernel
-  return {1, (p->max_disp + kWave - 1) / kWave};
-}
-
-// Workspace of stereo_solve: the FP16 exponent map, then the WTA partial minima.
+// Workspace of stereo_solve: the FP16 exponent map, then the WTA partial minima
+// of the disparity chunks (one V lane per disparity, 64-disparity chunks).
 struct WsLayout {
   size_t ex, part_val, part_idx, total;
 };
 size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+int wta_chunks(const zdt_params* p) { return (p->max_disp + kWave - 1) / kWave; }
 WsLayout ws_layout(const zdt_params* p) {
   WsLayout L{};
   const size_t npix = (size_t)p->width * p->height;
@@ -270,49 +345,110 @@ WsLayout ws_layout(const zdt_params* p) {
     L.ex = o;
     o += align256(npix * nck);
   }
-  const VWta vw = v_wta_shape(p, v_split(p).seg);
-  if (p->dt_iters > 0 && vw.nchunks > 1) {
+  if (p->dt_iters > 0 && wta_chunks(p) > 1) {
     L.part_val = o;
-    o += align256((size_t)vw.nchunks * npix * sizeof(float));
+    o += align256((size_t)wta_chunks(p) * npix * sizeof(float));
     L.part_idx = o;
-    o += align256((size_t)vw.nchunks * npix * sizeof(int32_t));
+    o += align256((size_t)wta_chunks(p) * npix * sizeof(int32_t));
   }
   L.total = o;
   return L;
 }
 
-int run_hpair(const zdt_params* p, const uint8_t* guide, void* vol, float scale, int8_t* ex, hipStream_t s) {
-  return run_h_mode(p, p->vol_dtype, kHPair, nullptr, nullptr, guide, vol, scale, ex, s);
-}
+// One pair's device buffers.
+struct JobPtrs {
+  const uint8_t* left;
+  const uint8_t* right;
+  int32_t* disp;
+  void* vol;
+  void* ws;
+};
 
-int run_vpair(const zdt_params* p, const uint8_t* guide, void* vol, float scale, int8_t* ex, hipStream_t s) {
-  const Split sp = v_split(p);
-  VArgs a = make_vargs(p, guide, vol, scale, sp);
-  a.ex = ex;
-  return dispatch_v(p->vol_dtype, sp.seg, 1, false, a, (p->max_disp + kWave - 1) / kWave, s);
-}
-
-int run_vpair_wta(const zdt_params* p, const uint8_t* guide, void* vol, float scale, int8_t* ex, int32_t* disp,
-                  void* ws, hipStream_t s) {
-  const Split sp = v_split(p);
-  const VWta vw = v_wta_shape(p, sp.seg);
-  VArgs va = make_vargs(p, guide, vol, scale, sp);
-  va.ex = ex;
-  if (vw.nchunks == 1) {
-    va.disp = disp;
-    return dispatch_v(p->vol_dtype, sp.seg, vw.dpl, true, va, 1, s);
-  }
+// stereo_solve for n <= kMaxJobs pairs that share every parameter: each stage
+// is one launch over all of them (grid z = job).
+int solve_group(const zdt_params* p, const JobPtrs* jobs, int n, hipStream_t s) {
+  if (n < 1 || n > kMaxJobs) return fail(ZDT_EINVAL, "solve_group: %d jobs", n);
+  const Plan pl = plan_for(p);
   const WsLayout L = ws_layout(p);
+  const bool scaled = p->vol_dtype == ZDT_F16;  // exponent-scaled FP16 working volume
+  const bool multi = wta_chunks(p) > 1;
   const size_t npix = (size_t)p->width * p->height;
-  va.part_val = (float*)((char*)ws + L.part_val);
-  va.part_idx = (int32_t*)((char*)ws + L.part_idx);
-  int rc = dispatch_v(p->vol_dtype, sp.seg, vw.dpl, true, va, vw.nchunks, s);
-  if (rc) return rc;
-  const int threads = 256;
-  return launch("wta_combine", wta_combine_kernel, dim3((unsigned)((npix + threads - 1) / threads)), dim3(threads), 0,
-                s, (const float*)va.part_val, (const int32_t*)va.part_idx, vw.nchunks, (int)npix, disp);
+  HJobs ht{};
+  VJobs vt{};
+  WJobs wt{};
+  for (int i = 0; i < n; ++i) {
+    const JobPtrs& j = jobs[i];
+    const uint8_t* guide = (p->flags & ZDT_FLAG_GUIDE_TARGET) ? j.right : j.left;
+    int8_t* ex = scaled ? (int8_t*)((char*)j.ws + L.ex) : nullptr;
+    float* pv = multi ? (float*)((char*)j.ws + L.part_val) : nullptr;
+    int32_t* pi = multi ? (int32_t*)((char*)j.ws + L.part_idx) : nullptr;
+    ht.j[i] = {j.left, j.right, guide, j.vol, ex};
+    vt.j[i] = {guide, j.vol, ex, multi ? nullptr : j.disp, pv, pi};
+    wt.j[i] = {pv, pi, j.disp};
+  }
+  // An FP16 working volume keeps per-(pixel, chunk) exponents and needs no
+  // global scale; the other types take the (1-K)-per-pass normalisation.
+  const float sc = scaled ? 1.0f : pair_scale(p);
+  const HArgs ha = make_hargs(p, sc);
+  const VArgs va = make_vargs(p, sc);
+  // sweep 1: cost fused with L, R; then U, D.  Sweeps 2..I: L, R; U, D.  The
+  // last U, D pair carries the WTA and writes no volume.
+  int rc = launch_h(p, p->vol_dtype, kCostHPair, scaled, ha, ht, n, pl, s);
+  for (int it = 0; rc == ZDT_OK && it < p->dt_iters; ++it) {
+    if (it > 0 && (rc = launch_h(p, p->vol_dtype, kHPair, scaled, ha, ht, n, pl, s))) break;
+    rc = launch_v(p, scaled, it + 1 == p->dt_iters, va, vt, n, pl, s);
+  }
+  if (rc == ZDT_OK && multi) {
+    const int threads = 256;
+    rc = launch("wta_combine", wta_combine_kernel, dim3((unsigned)((npix + threads - 1) / threads), 1, n),
+                dim3(threads), 0, s, wt, wta_chunks(p), (int)npix);
+  }
+  return rc;
 }
 
+// The raw-cost path (dt_iters = 0): streamed cost volume, then the WTA.
+int solve_raw(const zdt_params* p, const JobPtrs& j, hipStream_t s) {
+  HJobs t{};
+  t.j[0] = {j.left, j.right, nullptr, j.vol, nullptr};
+  const Plan pl = plan_for(p);
+  int rc = launch_h(p, p->vol_dtype, kCost, false, make_hargs(p, 1.0f), t, 1, pl, s);
+  if (rc) return rc;
+  return dispatch_wta(p->vol_dtype, j.vol, p->width * p->height, p->max_disp, j.disp, s);
+}
+
+int check_job(const zdt_params* p, const uint8_t* left, const uint8_t* right, const int32_t* disp, const void* vol,
+              const void* ws, const char* who) {
+  int rc = check_params(p, who);
+  if (rc) return rc;
+  if (!left || !right || !disp || !vol) return fail(ZDT_EINVAL, "%s: NULL image, disparity or volume pointer", who);
+  if (p->dt_iters > 0) {
+    const size_t need = ws_layout(p).total;
+    if (need && !ws) return fail(ZDT_EINVAL, "%s: a workspace of %zu B is required", who, need);
+  }
+  return ZDT_OK;
+}
+
+zdt_plan to_c(const Plan& pl) { return zdt_plan{pl.h_lanes, pl.h_seg, pl.v_seg, 0}; }
+
+// Plan cache file: one line per shape,
+//   zdt-plan W H D R dtype : h_lanes h_seg v_seg  (best_us)
+bool read_cached_plan(const char* path, const zdt_params* p, Plan* out) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[256];
+  bool found = false;
+  while (std::fgets(line, sizeof line, f)) {
+    int W, H, D, R, dt, hl, hs, vs;
+    if (std::sscanf(line, "zdt-plan %d %d %d %d %d : %d %d %d", &W, &H, &D, &R, &dt, &hl, &hs, &vs) == 8 &&
+        W == p->width && H == p->height && D == p->max_disp && R == p->radius && dt == p->vol_dtype &&
+        h_plan_ok(W, hl, hs) && v_plan_ok(H, vs)) {
+      *out = {hl, hs, vs};
+      found = true;  // the last matching line wins
+    }
+  }
+  std::fclose(f);
+  return found;
+}
 }  // namespace
 
 // =================================================================== C ABI
@@ -335,7 +471,9 @@ int zncc_cost_volume(const zdt_params* p, const uint8_t* left, const uint8_t* ri
   int rc = check_params(p, "zncc_cost_volume");
   if (rc) return rc;
   if (!left || !right || !cost) return fail(ZDT_EINVAL, "zncc_cost_volume: NULL image or volume pointer");
-  return run_h_mode(p, p->vol_dtype, kCost, left, right, nullptr, cost, 1.0f, nullptr, (hipStream_t)stream);
+  HJobs t{};
+  t.j[0] = {left, right, nullptr, cost, nullptr};
+  return launch_h(p, p->vol_dtype, kCost, false, make_hargs(p, 1.0f), t, 1, plan_for(p), (hipStream_t)stream);
 }
 
 int zncc_window_sums(const zdt_params* p, const uint8_t* left, const uint8_t* right, int32_t* s_l, int32_t* s_ll,
@@ -343,13 +481,15 @@ int zncc_window_sums(const zdt_params* p, const uint8_t* left, const uint8_t* ri
   int rc = check_params(p, "zncc_window_sums");
   if (rc) return rc;
   if (!left || !right) return fail(ZDT_EINVAL, "zncc_window_sums: NULL image pointer");
-  HArgs sums{};
-  sums.s_rt = s_rt;
-  sums.s_l = s_l;
-  sums.s_ll = s_ll;
-  sums.s_t = s_t;
-  sums.s_tt = s_tt;
-  return run_h_mode(p, ZDT_F32, kSums, left, right, nullptr, nullptr, 1.0f, nullptr, (hipStream_t)stream, &sums);
+  HArgs a = make_hargs(p, 1.0f);
+  a.s_rt = s_rt;
+  a.s_l = s_l;
+  a.s_ll = s_ll;
+  a.s_t = s_t;
+  a.s_tt = s_tt;
+  HJobs t{};
+  t.j[0] = {left, right, nullptr, nullptr, nullptr};
+  return launch_h(p, ZDT_F32, kSums, false, a, t, 1, plan_for(p), (hipStream_t)stream);
 }
 
 int dt_aggregate(const zdt_params* p, const uint8_t* guide, void* cost, double* applied_scale, void* stream) {
@@ -358,9 +498,14 @@ int dt_aggregate(const zdt_params* p, const uint8_t* guide, void* cost, double* 
   if (!guide || !cost) return fail(ZDT_EINVAL, "dt_aggregate: NULL guide or volume pointer");
   hipStream_t s = (hipStream_t)stream;
   const float sc = pair_scale(p);
+  const Plan pl = plan_for(p);
+  HJobs ht{};
+  ht.j[0] = {nullptr, nullptr, guide, cost, nullptr};
+  VJobs vt{};
+  vt.j[0] = {guide, cost, nullptr, nullptr, nullptr, nullptr};
   for (int it = 0; it < p->dt_iters; ++it) {
-    if ((rc = run_hpair(p, guide, cost, sc, nullptr, s))) return rc;
-    if ((rc = run_vpair(p, guide, cost, sc, nullptr, s))) return rc;
+    if ((rc = launch_h(p, p->vol_dtype, kHPair, false, make_hargs(p, sc), ht, 1, pl, s))) return rc;
+    if ((rc = launch_v(p, false, false, make_vargs(p, sc), vt, 1, pl, s))) return rc;
   }
   if (applied_scale) *applied_scale = total_scale(p);
   return ZDT_OK;
@@ -375,32 +520,165 @@ int wta_disparity(const zdt_params* p, const void* cost, int32_t* disp, void* st
 
 int stereo_solve(const zdt_params* p, const uint8_t* left, const uint8_t* right, int32_t* disp, void* vol, void* ws,
                  void* stream) {
-  int rc = check_params(p, "stereo_solve");
+  int rc = check_job(p, left, right, disp, vol, ws, "stereo_solve");
   if (rc) return rc;
-  if (!left || !right || !disp || !vol)
-    return fail(ZDT_EINVAL, "stereo_solve: NULL image, disparity or volume pointer");
-  hipStream_t s = (hipStream_t)stream;
-  const uint8_t* guide = (p->flags & ZDT_FLAG_GUIDE_TARGET) ? right : left;
-  if (p->dt_iters == 0) {
-    if ((rc = run_h_mode(p, p->vol_dtype, kCost, left, right, nullptr, vol, 1.0f, nullptr, s))) return rc;
-    return dispatch_wta(p->vol_dtype, vol, p->width * p->height, p->max_disp, disp, s);
+  const JobPtrs j{left, right, disp, vol, ws};
+  if (p->dt_iters == 0) return solve_raw(p, j, (hipStream_t)stream);
+  return solve_group(p, &j, 1, (hipStream_t)stream);
+}
+
+int stereo_solve_batch(const zdt_job* jobs, int32_t n, void* stream) {
+  if (n < 0 || (n > 0 && !jobs)) return fail(ZDT_EINVAL, "stereo_solve_batch: %d jobs at %p", n, (const void*)jobs);
+  for (int i = 0; i < n; ++i) {
+    const zdt_job& j = jobs[i];
+    int rc = check_job(&j.params, j.left, j.right, j.disp, j.vol, j.ws, "stereo_solve_batch");
+    if (rc) return fail(rc, "stereo_solve_batch: job %d: %s", i, zdt_last_error());
   }
-  const WsLayout L = ws_layout(p);
-  if (L.total && !ws) return fail(ZDT_EINVAL, "stereo_solve: a workspace of %zu B is required", L.total);
-  // An FP16 working volume keeps per-(pixel, chunk) exponents and needs no
-  // global scale; the other types take the (1-K)-per-pass normalisation.
-  int8_t* ex = p->vol_dtype == ZDT_F16 ? (int8_t*)((char*)ws + L.ex) : nullptr;
-  const float sc = ex ? 1.0f : pair_scale(p);
-  // sweep 1: cost fused with L, R; then U, D.  Sweeps 2..I: L, R; U, D.  The
-  // last U, D pair carries the WTA and writes no volume.
-  if ((rc = run_h_mode(p, p->vol_dtype, kCostHPair, left, right, guide, vol, sc, ex, s))) return rc;
-  for (int it = 0; it < p->dt_iters; ++it) {
-    if (it > 0 && (rc = run_hpair(p, guide, vol, sc, ex, s))) return rc;
-    if (it + 1 < p->dt_iters) {
-      if ((rc = run_vpair(p, guide, vol, sc, ex, s))) return rc;
-    } else if ((rc = run_vpair_wta(p, guide, vol, sc, ex, disp, ws, s))) {
-      return rc;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<char> done(n, 0);
+  std::vector<JobPtrs> group;
+  for (int i = 0; i < n; ++i) {
+    if (done[i]) continue;
+    const zdt_params& p = jobs[i].params;
+    // jobs with identical parameters, in submission order, kMaxJobs per launch
+    group.clear();
+    for (int k = i; k < n; ++k) {
+      if (done[k] || std::memcmp(&jobs[k].params, &p, sizeof p) != 0) continue;
+      done[k] = 1;
+      group.push_back({jobs[k].left, jobs[k].right, jobs[k].disp, jobs[k].vol, jobs[k].ws});
     }
+    for (size_t g0 = 0; g0 < group.size(); g0 += kMaxJobs) {
+      const int m = (int)std::min<size_t>(kMaxJobs, group.size() - g0);
+      int rc = ZDT_OK;
+      if (p.dt_iters == 0) {
+        for (int k = 0; k < m && rc == ZDT_OK; ++k) rc = solve_raw(&p, group[g0 + k], s);
+      } else {
+        rc = solve_group(&p, group.data() + g0, m, s);
+      }
+      if (rc) return rc;
+    }
+  }
+  return ZDT_OK;
+}
+
+int zdt_plan_candidates(const zdt_params* p, zdt_plan* out, int max) {
+  int rc = check_params(p, "zdt_plan_candidates");
+  if (rc) return rc;
+  if (max < 0 || (max > 0 && !out)) return fail(ZDT_EINVAL, "zdt_plan_candidates: bad output array");
+  const std::vector<Plan> c = plan_candidates(p);
+  for (int i = 0; i < max && i < (int)c.size(); ++i) out[i] = to_c(c[i]);
+  return (int)c.size();
+}
+
+int zdt_get_plan(const zdt_params* p, zdt_plan* out) {
+  int rc = check_params(p, "zdt_get_plan");
+  if (rc) return rc;
+  if (!out) return fail(ZDT_EINVAL, "zdt_get_plan: NULL output");
+  *out = to_c(plan_for(p));
+  return ZDT_OK;
+}
+
+int zdt_set_plan(const zdt_params* p, const zdt_plan* plan) {
+  int rc = check_params(p, "zdt_set_plan");
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  if (!plan) {
+    g_plans.erase(plan_key(p));
+    return ZDT_OK;
+  }
+  if (plan->reserved != 0 || !h_plan_ok(p->width, plan->h_lanes, plan->h_seg) || !v_plan_ok(p->height, plan->v_seg))
+    return fail(ZDT_EINVAL, "zdt_set_plan: plan (%d, %d, %d) does not fit %dx%d", plan->h_lanes, plan->h_seg,
+                plan->v_seg, p->width, p->height);
+  g_plans[plan_key(p)] = {plan->h_lanes, plan->h_seg, plan->v_seg};
+  return ZDT_OK;
+}
+
+int zdt_autotune(const zdt_params* p, const char* cache_path, zdt_plan* chosen, void* stream) {
+  int rc = check_params(p, "zdt_autotune");
+  if (rc) return rc;
+  Plan best{};
+  if (cache_path && read_cached_plan(cache_path, p, &best)) {
+    const zdt_plan c = to_c(best);
+    if ((rc = zdt_set_plan(p, &c))) return rc;
+    if (chosen) *chosen = c;
+    return ZDT_OK;
+  }
+  if (p->dt_iters == 0) {  // nothing register-resident to tune
+    if (chosen) *chosen = to_c(plan_for(p));
+    return ZDT_OK;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const size_t img = (size_t)p->pitch * p->height, npix = (size_t)p->width * p->height;
+  const size_t vbytes = npix * p->max_disp * dtype_size(p->vol_dtype), wbytes = ws_layout(p).total;
+  uint8_t *left = nullptr, *right = nullptr;
+  int32_t* disp = nullptr;
+  void *vol = nullptr, *ws = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto release = [&]() {
+    (void)hipFree(left);
+    (void)hipFree(right);
+    (void)hipFree(disp);
+    (void)hipFree(vol);
+    (void)hipFree(ws);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  if (hipMalloc((void**)&left, img) != hipSuccess || hipMalloc((void**)&right, img) != hipSuccess ||
+      hipMalloc((void**)&disp, npix * 4) != hipSuccess || hipMalloc(&vol, vbytes) != hipSuccess ||
+      (wbytes && hipMalloc(&ws, wbytes) != hipSuccess) || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess) {
+    release();
+    return fail(ZDT_EHIP, "zdt_autotune: cannot allocate the %zu B trial buffers", 2 * img + npix * 4 + vbytes + wbytes);
+  }
+  {  // a textured trial pair (timings do not depend on the values)
+    std::vector<uint8_t> h(img);
+    uint32_t x = 12345u;
+    for (auto& v : h) v = (uint8_t)((x = x * 1664525u + 1013904223u) >> 24);
+    if (hipMemcpy(left, h.data(), img, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(right, h.data(), img, hipMemcpyHostToDevice) != hipSuccess) {
+      release();
+      return fail(ZDT_EHIP, "zdt_autotune: cannot upload the trial pair");
+    }
+  }
+  const JobPtrs job{left, right, disp, vol, ws};
+  const std::vector<Plan> cands = plan_candidates(p);
+  constexpr int kWarm = 2, kReps = 5;
+  float best_ms = 0.0f;
+  for (size_t c = 0; c < cands.size(); ++c) {
+    {
+      std::lock_guard<std::mutex> lk(g_plan_mu);
+      g_plans[plan_key(p)] = cands[c];
+    }
+    for (int r = 0; r < kWarm && rc == ZDT_OK; ++r) rc = solve_group(p, &job, 1, s);
+    if (rc == ZDT_OK && hipEventRecord(e0, s) != hipSuccess) rc = fail(ZDT_EHIP, "zdt_autotune: event record");
+    for (int r = 0; r < kReps && rc == ZDT_OK; ++r) rc = solve_group(p, &job, 1, s);
+    float ms = 0.0f;
+    if (rc == ZDT_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                         hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      rc = fail(ZDT_EHIP, "zdt_autotune: timing failed");
+    if (rc) break;
+    if (c == 0 || ms < best_ms) {
+      best_ms = ms;
+      best = cands[c];
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    if (rc == ZDT_OK)
+      g_plans[plan_key(p)] = best;
+    else
+      g_plans.erase(plan_key(p));
+  }
+  if (hipStreamSynchronize(s) != hipSuccess && rc == ZDT_OK) rc = fail(ZDT_EHIP, "zdt_autotune: stream sync");
+  release();
+  if (rc) return rc;
+  if (chosen) *chosen = to_c(best);
+  if (cache_path) {
+    FILE* f = std::fopen(cache_path, "a");
+    if (!f) return fail(ZDT_EINVAL, "zdt_autotune: cannot append to %s", cache_path);
+    std::fprintf(f, "zdt-plan %d %d %d %d %d : %d %d %d  (%.1f us)\n", p->width, p->height, p->max_disp, p->radius,
+                 p->vol_dtype, best.h_lanes, best.h_seg, best.v_seg, 1000.0 * best_ms / kReps);
+    std::fclose(f);
   }
   return ZDT_OK;
 }

@@ -1,0 +1,197 @@
+"""Multi-job launches, tile plans and the autotuner on the GPU.
+
+  - stereo_solve_batch gives, job for job, the same bits as separate
+    stereo_solve calls (mixed shapes, types and sweep counts; more jobs of one
+    shape than one launch takes);
+  - every tile plan a shape admits agrees with the FP64 oracle to the usual
+    end-to-end bar (FP32: mismatches only at near-ties of the oracle's own
+    aggregated costs; FP16: <= 0.1 % of disparities);
+  - the largest batch shape, 1920x1080 with D = 256, agrees with the oracle
+    over every pixel (oracle run slice by slice on the host);
+  - the autotuner pins one of the candidates and caches it.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2212_00476_amd import scenes
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+import paper_2212_00476_amd as zdt  # noqa: E402
+
+DT_REL = 3e-5
+ORACLE_THREADS = min(16, os.cpu_count() or 1)
+
+
+def note(msg):
+    print(msg, flush=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def pair_for(W, H, D, seed=0):
+    ds = tuple(sorted({max(0, min(D - 1, k)) for k in (1, D // 3, (2 * D) // 3)}))
+    return scenes.bands_pair(W=W, H=H, D=D, seed=seed, band_disps=ds)
+
+
+class Job:
+    def __init__(self, W, H, D, r, dtype, iters, seed):
+        self.p = zdt.params(W, H, D, r, dt_iters=iters, vol_dtype=dtype)
+        pr = pair_for(W, H, D, seed)
+        self.left, self.right = dev(pr.left), dev(pr.right)
+        self.disp = torch.full((H, W), -1, dtype=torch.int32, device="cuda")
+        self.vol = torch.empty((H, W, D), dtype=zdt.torch_dtype(dtype), device="cuda")
+        ws = zdt.workspace_size(self.p)
+        self.ws = torch.empty(ws, dtype=torch.uint8, device="cuda") if ws else None
+
+    def tuple(self):
+        return (self.p, self.left, self.right, self.disp, self.vol, self.ws)
+
+    def solve_alone(self):
+        disp = torch.full_like(self.disp, -1)
+        zdt.stereo_solve(self.p, self.left, self.right, disp, self.vol, self.ws)
+        return disp
+
+
+MIX = [(320, 96, 32, 4, zdt.ZDT_F32, 3), (320, 96, 32, 4, zdt.ZDT_F32, 3), (320, 96, 32, 4, zdt.ZDT_F16, 3),
+       (100, 17, 65, 3, zdt.ZDT_F32, 3), (320, 96, 32, 4, zdt.ZDT_F32, 3), (37, 23, 11, 2, zdt.ZDT_BF16, 3),
+       (129, 33, 130, 0, zdt.ZDT_F32, 1), (100, 17, 65, 3, zdt.ZDT_F32, 3), (50, 40, 1, 1, zdt.ZDT_F32, 0),
+       (320, 96, 32, 4, zdt.ZDT_F16, 3), (200, 150, 200, 2, zdt.ZDT_F16, 2)]
+
+
+def test_batch_equals_separate_calls_mixed():
+    note("batch of %d mixed jobs" % len(MIX))
+    jobs = [Job(*m, seed=20 + i) for i, m in enumerate(MIX)]
+    zdt.stereo_solve_batch([j.tuple() for j in jobs])
+    torch.cuda.synchronize()
+    got = [j.disp.clone() for j in jobs]
+    for i, j in enumerate(jobs):
+        alone = j.solve_alone()
+        torch.cuda.synchronize()
+        assert (alone >= 0).all()
+        assert torch.equal(got[i], alone), i
+
+
+def test_batch_more_jobs_than_one_launch():
+    n = 35
+    note("batch of %d jobs of one shape" % n)
+    jobs = [Job(64, 24, 16, 2, zdt.ZDT_F16, 3, seed=100 + i) for i in range(n)]
+    zdt.stereo_solve_batch([j.tuple() for j in jobs])
+    torch.cuda.synchronize()
+    got = [j.disp.clone() for j in jobs]
+    for i, j in enumerate(jobs):
+        assert torch.equal(got[i], j.solve_alone()), i
+
+
+def _near_tie_ok(disp, cagg):
+    dmin = cagg.min(axis=2)
+    dmax = np.abs(cagg).max(axis=2)
+    picked = np.take_along_axis(cagg, disp[:, :, None].astype(np.int64), axis=2)[:, :, 0]
+    slack = picked - dmin
+    return slack, slack <= DT_REL * dmax
+
+
+PLAN_SHAPES = [(320, 96, 32, 4), (90, 200, 8, 2), (640, 48, 40, 3)]
+
+
+@pytest.mark.parametrize("shape", PLAN_SHAPES, ids=["%dx%d_d%d_r%d" % s for s in PLAN_SHAPES])
+def test_every_plan_matches_oracle_fp32(shape):
+    W, H, D, r = shape
+    pr = pair_for(W, H, D, seed=7)
+    o_disp, cagg = oracle.stereo_solve(pr.left, pr.right, D, r, 20.0, 0.1, 3, keep_volume=True)
+    p = zdt.params(W, H, D, r)
+    plans = zdt.plan_candidates(p)
+    L, R = dev(pr.left), dev(pr.right)
+    try:
+        for plan in plans:
+            note(f"plan {plan} on {shape}")
+            zdt.set_plan(p, plan)
+            disp = zdt.Solver(p)(L, R)
+            torch.cuda.synchronize()
+            slack, ok = _near_tie_ok(disp.cpu().numpy(), cagg)
+            assert ok.all(), (plan, slack[~ok].max())
+    finally:
+        zdt.set_plan(p, None)
+
+
+def test_every_plan_matches_oracle_fp16():
+    W, H, D, r = 320, 96, 32, 4
+    pr = scenes.bands_pair()
+    o_disp = oracle.stereo_solve(pr.left, pr.right, D, r, 20.0, 0.1, 3)
+    p = zdt.params(W, H, D, r, vol_dtype=zdt.ZDT_F16)
+    L, R = dev(pr.left), dev(pr.right)
+    try:
+        for plan in zdt.plan_candidates(p):
+            zdt.set_plan(p, plan)
+            disp = zdt.Solver(p)(L, R).cpu().numpy()
+            mism = (disp != o_disp).mean()
+            note(f"plan {plan}: FP16 mismatch {100 * mism:.4f} %")
+            assert mism <= 1e-3, plan
+    finally:
+        zdt.set_plan(p, None)
+
+
+def _streamed_oracle_check(pr, D, r, disp):
+    """Near-tie check of `disp` against the oracle's aggregated volume, computed
+    32 disparity slices at a time (the whole volume would not fit in memory)."""
+    H, W = pr.left.shape
+    best = np.full((H, W), np.inf)
+    at_gpu = np.full((H, W), np.nan)
+    amax = np.zeros((H, W))
+    arg = np.zeros((H, W), np.int32)
+    for d0 in range(0, D, 32):
+        ds = list(range(d0, min(D, d0 + 32)))
+        c = oracle.solve_slices(pr.left, pr.right, r, ds, 20.0, 0.1, 3, threads=ORACLE_THREADS)
+        for k, d in enumerate(ds):
+            better = c[k] < best                       # strict: the lowest d wins ties
+            best = np.where(better, c[k], best)
+            arg = np.where(better, d, arg)
+            amax = np.maximum(amax, np.abs(c[k]))
+            at_gpu = np.where(disp == d, c[k], at_gpu)
+        del c
+    slack = at_gpu - best
+    return arg, slack, slack <= DT_REL * amax
+
+
+_BIG = {}
+
+
+@pytest.mark.parametrize("dtype", [zdt.ZDT_F32, zdt.ZDT_F16], ids=["f32", "f16"])
+def test_full_size_1920x1080_d256(dtype):
+    W, H, D, r = 1920, 1080, 256, 4
+    pr = scenes.workload("planes_1920x1080_d256")
+    note(f"1920x1080 D=256 dtype={dtype}: GPU solve")
+    p = zdt.params(W, H, D, r, vol_dtype=dtype)
+    disp = zdt.Solver(p)(dev(pr.left), dev(pr.right)).cpu().numpy()
+    if "arg" not in _BIG or dtype == zdt.ZDT_F32:
+        note(f"  oracle: 256 slices of 1920x1080 on {ORACLE_THREADS} threads, 32 at a time")
+        arg, slack, ok = _streamed_oracle_check(pr, D, r, disp)
+        _BIG["arg"] = arg
+    mism = (disp != _BIG["arg"]).mean()
+    note(f"  mismatch {100 * mism:.4f} %")
+    if dtype == zdt.ZDT_F32:
+        assert ok.all(), slack[~ok].max()
+    else:
+        assert mism <= 1e-3
+
+
+def test_autotune_pins_a_candidate_and_caches_it(tmp_path):
+    p = zdt.params(320, 96, 32, 4, vol_dtype=zdt.ZDT_F16)
+    cache = tmp_path / "plans.txt"
+    try:
+        chosen = zdt.autotune(p, str(cache))
+        note(f"autotune 320x96 D=32 F16 -> {chosen}")
+        assert chosen in zdt.plan_candidates(p)
+        assert zdt.get_plan(p) == chosen
+        text = cache.read_text()
+        assert text.startswith("zdt-plan 320 96 32 4 1 : ")
+        zdt.set_plan(p, None)
+        assert zdt.autotune(p, str(cache)) == chosen     # from the cache this time
+        assert cache.read_text() == text
+    finally:
+        zdt.set_plan(p, None)

@@ -5,7 +5,10 @@ with sigma_s = 20, sigma_r = 0.1 and 3 sweeps, WTA -- the cost, all twelve DT
 passes and the WTA, on inputs already resident in HBM.  The headline value is
 FP32-volume throughput in G cost evaluations per second (W*H*D per step); the
 same line carries the FP16 and BF16 forms, the unfused FP32 per-pair form, the
-roofline of the dominant kernel and the CPU oracle timed on a bounded sample.
+roofline of the dominant kernel, the CPU oracle timed on a bounded sample, a
+48-pair mixed-shape batch (FP16, autotuned plans) and the continuous-batching
+server under Poisson arrivals (p50 / p99 latency, with every served result
+checked against the same pair solved alone).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -88,6 +91,67 @@ def cpu_baseline(left, right, n_slices, threads):
                       "%.1f s wall on %d threads" % (len(ds), D, dt, threads)}
 
 
+BATCH = {"640x192_d64": 16, "1280x384_d128": 24, "1920x1080_d256": 8}
+POOLS = {"640x192_d64": 4, "1280x384_d128": 2, "1920x1080_d256": 1}
+
+
+def bench_batch(torch, zdt, reps=3):
+    """48 pairs of three shapes in one stereo_solve_batch call, FP16 volumes,
+    tile plans from the autotuner; against the same pairs solved one by one."""
+    from paper_2212_00476_amd import serving
+    pools = serving.make_pairs(POOLS)
+    plans, jobs, evals = {}, [], 0
+    for sh in serving.SHAPES:
+        p = zdt.params(sh.W, sh.H, sh.D, R, SIGMA_S, SIGMA_R, ITERS, vol_dtype=zdt.ZDT_F16)
+        plans[sh.name] = list(zdt.autotune(p))
+        dev_pairs = [(torch.from_numpy(q.left).cuda(), torch.from_numpy(q.right).cuda()) for q in pools[sh.name]]
+        wsz = zdt.workspace_size(p)
+        for i in range(BATCH[sh.name]):
+            left, right = dev_pairs[i % len(dev_pairs)]
+            jobs.append((p, left, right, torch.empty((sh.H, sh.W), dtype=torch.int32, device="cuda"),
+                         torch.empty((sh.H, sh.W, sh.D), dtype=torch.float16, device="cuda"),
+                         torch.empty(wsz, dtype=torch.uint8, device="cuda") if wsz else None))
+            evals += sh.W * sh.H * sh.D
+    ms_b = time_steps(lambda: zdt.stereo_solve_batch(jobs), reps, 1, torch)
+
+    def one_by_one():
+        for j in jobs:
+            zdt.stereo_solve(*j)
+    ms_s = time_steps(one_by_one, reps, 1, torch)
+    del jobs
+    torch.cuda.empty_cache()
+    return {"workload": "16x 640x192 D64 + 24x 1280x384 D128 + 8x 1920x1080 D256, 9x9, FP16 volumes",
+            "jobs": sum(BATCH.values()), "ms": round(ms_b, 3), "gcost_evals_per_s": round(evals / ms_b / 1e6, 2),
+            "pairs_per_s": round(sum(BATCH.values()) / ms_b * 1e3, 1), "one_by_one_ms": round(ms_s, 3),
+            "plans": plans}
+
+
+def bench_serving(torch, zdt, seconds):
+    """Poisson arrivals at 300 pairs/s of the three-shape mix through the
+    continuous-batching server (FP16 volumes, graphs), every result checked
+    against the pair solved alone; then the server's capacity (all requests
+    offered at 3000/s) next to plain FP32 per-pair solves of the same requests."""
+    from paper_2212_00476_amd import serving
+    pools = serving.make_pairs(POOLS)
+    npairs = {k: len(v) for k, v in pools.items()}
+    ex = serving.GpuExecutor(pools, vol_dtype=zdt.ZDT_F16, lanes=2)
+    reqs = serving.poisson_arrivals(300.0, seconds, serving.MIX, npairs, seed=5)
+    serving.serve(reqs, ex.scheduler(), ex)
+    poisson = serving.summarize(reqs, duration=seconds)
+    poisson.update({"offered_per_s": 300.0, "seconds": seconds})
+    burst = serving.poisson_arrivals(3000.0, 1.0, serving.MIX, npairs, seed=6)
+    serving.serve(burst, ex.scheduler(), ex)
+    cap = serving.summarize(burst)
+    served_cap = cap["pairs_per_s"]
+    vol_gb = round(ex.volume_bytes / 1e9, 2)
+    del ex
+    torch.cuda.empty_cache()
+    per_pair = serving.per_pair_capacity(burst, pools, zdt.ZDT_F32)
+    return {"poisson": poisson, "capacity_f16_served_pairs_per_s": served_cap,
+            "capacity_f32_per_pair_pairs_per_s": round(per_pair, 1), "capacity_requests": len(burst),
+            "capacity_mismatched": cap["mismatched"], "lane_volumes_gb": vol_gb}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +161,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for rocprofv3 byte counters)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="length of the served Poisson run (0: skip)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 48-pair batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the whole pair on a single MI355X "
@@ -178,6 +244,9 @@ def main():
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes": abytes, "avg_us": round(avg_s * 1e6, 3)}
 
+    batch = None if args.no_batch else bench_batch(torch, zdt)
+    served = bench_serving(torch, zdt, args.serve_seconds) if args.serve_seconds > 0 else None
+
     cpu = None
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)
@@ -193,6 +262,8 @@ def main():
                    "parallelism": "single-gpu"},
         "fps": f32["fps"], "forms": forms, "kernels_f32": kernels, "kernels_f16": kernels_f16,
         "kernels_bf16": kernels_bf16, "roofline": roofline, "cpu_baseline": cpu,
+        "p99_ms_served": served["poisson"]["p99_ms"] if served else None,
+        "batch": batch, "serving": served,
     }
     print(json.dumps(line))
 

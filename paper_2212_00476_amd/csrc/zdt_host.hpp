@@ -20,18 +20,16 @@ bool prof_begin(ProfRec& rec, hipStream_t s);
 void prof_end(ProfRec& rec, hipStream_t s);
 
 // Every kernel keeps its working set in registers and LDS; one that needs
-// more per-lane scratch than this is refused with ZDT_EUNSUPPORTED (checked
-// once per kernel) rather than launched.
+// more per-lane scratch than this is refused with ZDT_EUNSUPPORTED rather than
+// launched.  The check, and raising a kernel's dynamic-LDS limit above 64 KB,
+// happen on the first launch that needs them only, so a warmed-up sequence of
+// launches can be captured into a graph with nothing else in between.
 constexpr int kMaxScratchBytes = 1024;
-int check_kernel(const void* kernel, const char* name);
+int prepare_kernel(const void* kernel, const char* name, size_t lds);
 
 template <typename Kernel, typename... A>
 int launch(const char* name, Kernel kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, A... args) {
-  if (const int rc = check_kernel((const void*)kernel, name)) return rc;
-  if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return fail(ZDT_EHIP, "%s: cannot reserve %zu B of LDS: %s", name, lds, hipGetErrorString(e));
-  }
+  if (const int rc = prepare_kernel((const void*)kernel, name, lds)) return rc;
   ProfRec rec{name, nullptr, nullptr};
   const bool prof = prof_begin(rec, s);
   hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);

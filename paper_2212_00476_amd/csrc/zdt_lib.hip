@@ -35,25 +35,34 @@ bool g_prof_on = false;
 std::vector<ProfRec> g_prof_pending;
 std::vector<std::pair<std::string, ProfAcc>> g_prof_acc;
 std::mutex g_kernel_mu;
-std::unordered_map<const void*, int> g_kernel_ok;  // kernel -> ZDT_OK or a ZDT_E* code
+struct KernelState {
+  int rc = ZDT_OK;       // ZDT_OK, or why the kernel is refused
+  size_t lds_limit = 0;  // dynamic LDS the kernel has been allowed above the 64 KB default
+};
+std::unordered_map<const void*, KernelState> g_kernel_ok;
 }  // namespace
 
-int check_kernel(const void* kernel, const char* name) {
+int prepare_kernel(const void* kernel, const char* name, size_t lds) {
   std::lock_guard<std::mutex> lk(g_kernel_mu);
   auto it = g_kernel_ok.find(kernel);
-  if (it != g_kernel_ok.end()) {
-    if (it->second != ZDT_OK) fail(it->second, "%s: kernel was refused (per-lane scratch too large)", name);
-    return it->second;
+  if (it == g_kernel_ok.end()) {
+    hipFuncAttributes attr{};
+    const hipError_t e = hipFuncGetAttributes(&attr, kernel);
+    if (e != hipSuccess) return fail(ZDT_EHIP, "%s: hipFuncGetAttributes: %s", name, hipGetErrorString(e));
+    KernelState st{};
+    if (attr.localSizeBytes > kMaxScratchBytes)
+      st.rc = fail(ZDT_EUNSUPPORTED, "%s: kernel needs %zu B of scratch per lane (limit %d)", name,
+                   (size_t)attr.localSizeBytes, kMaxScratchBytes);
+    it = g_kernel_ok.emplace(kernel, st).first;
   }
-  hipFuncAttributes attr{};
-  const hipError_t e = hipFuncGetAttributes(&attr, kernel);
-  if (e != hipSuccess) return fail(ZDT_EHIP, "%s: hipFuncGetAttributes: %s", name, hipGetErrorString(e));
-  int rc = ZDT_OK;
-  if (attr.localSizeBytes > kMaxScratchBytes)
-    rc = fail(ZDT_EUNSUPPORTED, "%s: kernel needs %zu B of scratch per lane (limit %d)", name,
-              (size_t)attr.localSizeBytes, kMaxScratchBytes);
-  g_kernel_ok.emplace(kernel, rc);
-  return rc;
+  KernelState& st = it->second;
+  if (st.rc != ZDT_OK) return fail(st.rc, "%s: kernel was refused (per-lane scratch too large)", name);
+  if (lds > 65536 && lds > st.lds_limit) {
+    const hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return fail(ZDT_EHIP, "%s: cannot reserve %zu B of LDS: %s", name, lds, hipGetErrorString(e));
+    st.lds_limit = lds;
+  }
+  return ZDT_OK;
 }
 
 int fail(int code, const char* fmt, ...) {

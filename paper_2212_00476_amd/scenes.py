@@ -63,17 +63,30 @@ class _Layer:
     a: float
     b: float
     c: float
-    tex: np.ndarray        # float64 [H][W+2], sampled at fractional x
+    tex: np.ndarray        # float64 texture; entry [j][i] is pixel (ox + i, oy + j), sampled at fractional x
     inside: callable       # (x, y) float arrays -> bool array
+    ox: int = 0
+    oy: int = 0
 
 
-def _sample(tex, x, y):
-    """Linear interpolation of tex along x at fractional x (integer rows y)."""
-    W = tex.shape[1]
-    x = np.clip(x, 0.0, W - 1.000001)
+def _in_box(fn, xlo, xhi, ylo, yhi):
+    """`fn` evaluated only at the points inside its bounding box (False outside)."""
+    def inside(x, y):
+        m = (x >= xlo) & (x <= xhi) & (y >= ylo) & (y <= yhi)
+        out = np.zeros(np.shape(x), bool)
+        out[m] = fn(x[m], y[m])
+        return out
+    return inside
+
+
+def _sample(L, x, y):
+    """Linear interpolation of a layer's texture along x at fractional x (integer rows y)."""
+    W = L.tex.shape[1]
+    x = np.clip(x - L.ox, 0.0, W - 1.000001)
     x0 = np.floor(x).astype(np.int64)
     f = x - x0
-    return tex[y, x0] * (1.0 - f) + tex[y, x0 + 1] * f
+    y = np.clip(y - L.oy, 0, L.tex.shape[0] - 1)
+    return L.tex[y, x0] * (1.0 - f) + L.tex[y, x0 + 1] * f
 
 
 def _render(layers, H, W, D, rng, gain, bias, noise, seed):
@@ -90,7 +103,7 @@ def _render(layers, H, W, D, rng, gain, bias, noise, seed):
     left = np.empty((H, W))
     for k, L in enumerate(layers):
         m = top == k
-        left[m] = L.tex[yi[m], xs[m].astype(np.int64)]
+        left[m] = L.tex[yi[m] - L.oy, xs[m].astype(np.int64) - L.ox]
     # right view: at x', the layer whose preimage x = (x' + a + c y) / (1 - b) is frontmost
     rtop = np.full((H, W), -1, np.int64)
     rd = np.full((H, W), -np.inf)
@@ -106,7 +119,7 @@ def _render(layers, H, W, D, rng, gain, bias, noise, seed):
     right = rng.uniform(0.0, 255.0, (H, W))
     for k, L in enumerate(layers):
         m = rtop == k
-        right[m] = gain * _sample(L.tex, rx[m], yi[m]) + bias
+        right[m] = gain * _sample(L, rx[m], yi[m]) + bias
     right = right + rng.normal(0.0, noise, (H, W))
     right = np.clip(np.rint(right), 0, 255).astype(np.uint8)
     left = np.clip(np.rint(left), 0, 255).astype(np.uint8)
@@ -193,8 +206,13 @@ def planes_pair(W=1280, H=384, D=128, seed=1, n_planes=None, noise=2.0):
             corners = [b * x + c * y for x in (xlo, xhi) for y in (ylo, yhi)]
         lo, hi = -min(corners), D - 1 - max(corners)
         a = rng.uniform(min(lo + dmax_bg, hi), hi) if hi > lo else lo
-        layers.append(_Layer(a=a, b=b, c=c, tex=_octave_texture(rng, H, W + 2, std=rng.uniform(25, 50)),
-                             inside=inside))
+        # texture and mask over the plane's bounding box only (columns one past
+        # each side for the interpolation of the target view)
+        ox, oy = max(0, int(np.floor(xlo)) - 1), max(0, int(np.floor(ylo)))
+        tw = min(W + 2, int(np.ceil(xhi)) + 3) - ox
+        th = min(H, int(np.ceil(yhi)) + 1) - oy
+        tex = _octave_texture(rng, max(th, 1), max(tw, 2), std=rng.uniform(25, 50))
+        layers.append(_Layer(a=a, b=b, c=c, tex=tex, inside=_in_box(inside, xlo, xhi, ylo, yhi), ox=ox, oy=oy))
     gain, bias = rng.uniform(0.8, 1.2), rng.uniform(-10.0, 10.0)
     return _render(layers, H, W, D, rng, gain, bias, noise, seed)
 

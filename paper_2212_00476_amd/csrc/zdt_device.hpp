@@ -405,6 +405,24 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
+// Wave minimum of B independent keys at once (results in lane 63): the six DPP
+// steps of wave_min_u32 applied stage by stage across the block, so no step
+// waits on the one just before it.
+template <int B>
+__device__ __forceinline__ void block_min_u32(uint32_t (&m)[B]) {
+  const int id = -1;
+#define ZDT_STAGE(CTRL, ROWMASK)                                                                     \
+  _Pragma("unroll") for (int i = 0; i < B; ++i) m[i] =                                              \
+      min(m[i], (uint32_t)__builtin_amdgcn_update_dpp(id, (int)m[i], CTRL, ROWMASK, 0xF, false));
+  ZDT_STAGE(0xB1, 0xF)   // quad_perm [1,0,3,2]
+  ZDT_STAGE(0x4E, 0xF)   // quad_perm [2,3,0,1]
+  ZDT_STAGE(0x141, 0xF)  // row_half_mirror
+  ZDT_STAGE(0x140, 0xF)  // row_mirror
+  ZDT_STAGE(0x142, 0xA)  // row_bcast:15
+  ZDT_STAGE(0x143, 0xC)  // row_bcast:31
+#undef ZDT_STAGE
+}
+
 // Exponent of the largest |v| over the lane's half-wave of 32 lanes (0 when
 // every value is 0).
 __device__ __forceinline__ int half_exponent(float v) {
@@ -884,35 +902,57 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs args, VJobs jobs) {
   } else {
     // argmin over the chunk's disparities, lowest d on ties (Eq. WTA1).  The
     // aggregated costs are >= 0, so their bit patterns order like the values
-    // (|.| folds a -0 onto +0); idle lanes hold +inf.
+    // (|.| folds a -0 onto +0); idle lanes hold +inf.  Pixels are reduced 8 at
+    // a time with their DPP chains interleaved; pixel k's (argmin, minimum)
+    // is kept by lane k % 64 in result register k / 64, and the segment's
+    // results leave in one store per register.
+    static_assert(DPL == 1, "the fused WTA takes one disparity per lane");
     const uint32_t kInf = 0x7F800000u;
+    constexpr int NR = (SEG + kWave - 1) / kWave;
+    constexpr int B = 8;
+    int rd[NR];
+    uint32_t rv[NR];
 #pragma unroll
-    for (int k = 0; k < SEG; ++k)
-      if (k < len) {
-        uint32_t v[DPL];
-        uint32_t best = kInf;
+    for (int r = 0; r < NR; ++r) {
+      rd[r] = 0;
+      rv[r] = kInf;
+    }
 #pragma unroll
-        for (int j = 0; j < DPL; ++j) {
-          v[j] = act[j] ? (__float_as_uint(c[j][k]) & 0x7FFFFFFFu) : kInf;
-          best = min(best, v[j]);
-        }
-        const uint32_t m = wave_min_u32(best);
-        int dbest = 0;
+    for (int k0 = 0; k0 < SEG; k0 += B) {
+      uint32_t v[B], m[B];
 #pragma unroll
-        for (int j = DPL - 1; j >= 0; --j) {
-          const unsigned long long mask = __ballot(v[j] == m);
-          if (mask) dbest = d0 + kWave * j + __builtin_ctzll(mask);
-        }
-        if (lane == 0) {
-          const size_t p = (size_t)(y0 + k) * W + x;
-          if (a.disp) {
-            a.disp[p] = dbest;
-          } else {
-            a.part_val[(size_t)chunk * W * H + p] = __uint_as_float(m);
-            a.part_idx[(size_t)chunk * W * H + p] = dbest;
-          }
+      for (int i = 0; i < B; ++i) {
+        const int k = min(k0 + i, SEG - 1);
+        v[i] = act[0] ? (__float_as_uint(c[0][k]) & 0x7FFFFFFFu) : kInf;
+        m[i] = v[i];
+      }
+      block_min_u32<B>(m);
+#pragma unroll
+      for (int i = 0; i < B; ++i) {
+        const int k = k0 + i;
+        if (k < SEG && k < len) {
+          const uint32_t mk = (uint32_t)__builtin_amdgcn_readlane((int)m[i], 63);
+          const unsigned long long mask = __ballot(v[i] == mk);
+          const int db = d0 + (int)__builtin_ctzll(mask);
+          const bool mine = lane == k % kWave;
+          rd[k / kWave] = mine ? db : rd[k / kWave];
+          rv[k / kWave] = mine ? mk : rv[k / kWave];
         }
       }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int k = r * kWave + lane;
+      if (k < len) {
+        const size_t p = (size_t)(y0 + k) * W + x;
+        if (a.disp) {
+          a.disp[p] = rd[r];
+        } else {
+          a.part_val[(size_t)chunk * W * H + p] = __uint_as_float(rv[r]);
+          a.part_idx[(size_t)chunk * W * H + p] = rd[r];
+        }
+      }
+    }
   }
 }
 

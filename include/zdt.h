@@ -136,14 +136,16 @@ int stereo_solve_batch(const zdt_job* jobs, int32_t n, void* stream);
  *            h_seg values) or 64 (up to 16 segments of at most h_seg values)
  *   h_seg    compiled horizontal segment length: 8, 20, 40, 60 (32 lanes) or
  *            16, 40, 80 (64 lanes)
- *   v_seg    compiled vertical segment length: 8, 12, 24, 48, 72 (one wave per
- *            segment, up to 16 per column)
+ *   v_lanes  lanes per vertical segment: 32 (two segments per wave, the
+ *            column split into an even number <= 32 of segments of exactly
+ *            v_seg rows) or 64 (up to 16 segments of at most v_seg rows)
+ *   v_seg    compiled vertical segment length: 12, 24, 36 (32 lanes) or
+ *            8, 12, 24, 48, 72 (64 lanes)
  * A plan changes only how rows and columns are cut into register-resident
  * segments; results agree with every other plan up to float32 rounding of the
  * segment-carry composition. */
 typedef struct zdt_plan {
-  int32_t h_lanes, h_seg, v_seg;
-  int32_t reserved; /* zero */
+  int32_t h_lanes, h_seg, v_lanes, v_seg;
 } zdt_plan;
 
 /* Every plan that fits params' shape, the default first: writes up to `max` of

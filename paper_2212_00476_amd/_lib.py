@@ -37,11 +37,11 @@ class ZdtJob(ctypes.Structure):
 
 
 class ZdtPlan(ctypes.Structure):
-    _fields_ = [("h_lanes", ctypes.c_int32), ("h_seg", ctypes.c_int32), ("v_seg", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+    _fields_ = [("h_lanes", ctypes.c_int32), ("h_seg", ctypes.c_int32), ("v_lanes", ctypes.c_int32),
+                ("v_seg", ctypes.c_int32)]
 
     def astuple(self):
-        return (self.h_lanes, self.h_seg, self.v_seg)
+        return (self.h_lanes, self.h_seg, self.v_lanes, self.v_seg)
 
 
 class ZdtError(RuntimeError):
@@ -150,7 +150,7 @@ def stereo_solve_batch(jobs, stream=None):
 
 
 def plan_candidates(p):
-    """Every tile plan (h_lanes, h_seg, v_seg) that fits the shape, the default first."""
+    """Every tile plan (h_lanes, h_seg, v_lanes, v_seg) that fits the shape, the default first."""
     lib = load()
     n = lib.zdt_plan_candidates(ctypes.byref(p), None, 0)
     if n < 0:
@@ -167,8 +167,8 @@ def get_plan(p):
 
 
 def set_plan(p, plan):
-    """Pin plan = (h_lanes, h_seg, v_seg) for p's shape; None restores the default."""
-    pl = None if plan is None else ctypes.byref(ZdtPlan(*plan, 0))
+    """Pin plan = (h_lanes, h_seg, v_lanes, v_seg) for p's shape; None restores the default."""
+    pl = None if plan is None else ctypes.byref(ZdtPlan(*plan))
     _check("zdt_set_plan", load().zdt_set_plan(ctypes.byref(p), pl))
 
 

@@ -37,14 +37,13 @@ namespace zdt {
 constexpr int kWave = 64;
 constexpr int kMaxWaves = 16;
 constexpr int kMaxSegs = 32;   // segments per H workgroup (LPS = 32: two per wave)
-constexpr int kExpBias = 14;   // FP16 working volume: value = fp16 * 2^(e - kExpBias)
-constexpr int kExpChunk = 32;  // disparities sharing one FP16 exponent (a half-wave)
+constexpr int kGainBias = 13;  // FP16 working volume: value = fp16 * 2^(floor(log2 G) - kGainBias)
 
 struct bf16 {
   uint16_t bits;
 };
-// FP16 element of a working volume that carries per-(pixel, 32-d chunk)
-// exponents (see "Narrow working volumes" below); stored like _Float16.
+// FP16 element of a working volume scaled per pixel by its DT gain (see
+// "Narrow working volumes" below); stored like _Float16.
 struct f16x {
   _Float16 h;
 };
@@ -185,10 +184,11 @@ __device__ __forceinline__ float carry_in(const float* B, const float* A, int se
 //   TS, TI [W+P]  target window sum and inverse deviation at x' = t-P-d0.
 //   WH[W+1]       W_L(x) for x in [0, W]; WH[0] = WH[W] = 0.
 //   EX, EX2 [16*64], EXS, EXS2 [kMaxSegs]   segment carries.
-//   XP[2][W]      exponents of the row's stored FP16 values, per 32-d chunk.
+//   GI, GO [W]    gains of the row before and after the pass pair (FP16
+//                 working volumes only).
 // ---------------------------------------------------------------------------
 struct HLayout {
-  int nLP, nTP, nTS, oLP, oLS, oLI, oTP, oTS, oTI, oWH, oEX, oEXS, oEX2, oEXS2, oXP, words;
+  int nLP, nTP, nTS, oLP, oLS, oLI, oTP, oTS, oTI, oWH, oEX, oEXS, oEX2, oEXS2, oGI, oGO, words;
 };
 
 __host__ __device__ constexpr HLayout h_layout(int W, int R, int LPS, int pad, bool zncc, bool dt, bool scaled) {
@@ -212,8 +212,10 @@ __host__ __device__ constexpr HLayout h_layout(int W, int R, int LPS, int pad, b
     L.oEXS = o; o += kMaxSegs;
     L.oEX2 = o; o += kMaxWaves * kWave;
     L.oEXS2 = o; o += kMaxSegs;
-    L.oXP = o;
-    if (scaled) o += 2 * (W + pad);  // FP16 exponents of the row, one line per half-wave chunk
+    L.oGI = o;
+    if (scaled) o += W + pad;  // FP16 working volume: the row's gains before and after the pair
+    L.oGO = o;
+    if (scaled) o += W + pad;
   }
   L.words = o;
   return L;
@@ -233,8 +235,9 @@ struct HArgs {
   int32_t* s_ll;
   int32_t* s_t;
   int32_t* s_tt;
-  int8_t* ex;      // FP16 working volume: per-(pixel, 32-d chunk) exponent map, else NULL
-  int segl, nseg;  // segment length and number of segments of a row
+  const float* g_in;  // FP16 working volume: gain map [H][W] of the stored input (sweeps 2..I)
+  float* g_out;       // and of the output (written by the workgroups of chunk 0)
+  int segl, nseg;     // segment length and number of segments of a row
   int nchunks;     // disparity chunks of LPS lanes per row
 };
 
@@ -247,7 +250,8 @@ struct HJob {
   const uint8_t* right;
   const uint8_t* guide;
   void* vol;
-  int8_t* ex;
+  const float* g_in;
+  float* g_out;
 };
 struct HJobs {
   HJob j[kMaxJobs];
@@ -373,13 +377,19 @@ __device__ __forceinline__ float zncc_cost_from(uint32_t srt, int sl, float il, 
 }
 
 // ---------------------------------------------------------------------------
-// Narrow working volumes.  An FP16 working volume (ex != NULL) stores each
-// (pixel, chunk of 32 disparities) with a shared power-of-two exponent e:
-// value = fp16 * 2^(e - 14).  The exponent is chosen from the chunk's maximum so
-// that the largest value lands in [2^14, 2^15); rescaling by a power of two is
-// exact, so only the FP16 rounding remains.  Without it the DT's gain, which
-// ranges from ~1 at edges to 1/(1-K) per pass in flat areas, pushes values out
-// of FP16's range.  BF16 and FP32 volumes store plain values.
+// Narrow working volumes.  The DT's gain ranges from ~1 per pass at edges to
+// 1/(1-K) per pass in flat areas, so aggregated values spread over far more
+// binades than FP16 holds.  An FP16 working volume is therefore stored scaled
+// per pixel by a power of two taken from the pixel's gain G: the DT of an
+// all-ones slice at the same stage (G >= 1; it depends only on the guide).
+// The passes are linear with positive weights and every cost lies in [0, 2],
+// so every value satisfies C <= 2 G; with k = floor(log2 G) the stored
+// C * 2^(kGainBias - k) stays below 2^15 for every disparity, without any
+// reduction over disparities.  Rescaling by a power of two is exact, so only
+// the FP16 rounding remains (relative 2^-11 down to C / G ~ 2^-28).  Each
+// workgroup computes the G line it needs with one wave (line_pair_gain); the
+// workgroup of disparity chunk 0 also writes it for the next stage.  BF16 and
+// FP32 volumes store plain values.
 // ---------------------------------------------------------------------------
 
 // Maximum of a non-negative 32-bit key over the 64 lanes (result from lane 63).
@@ -423,19 +433,70 @@ __device__ __forceinline__ void block_min_u32(uint32_t (&m)[B]) {
 #undef ZDT_STAGE
 }
 
-// Exponent of the largest |v| over the lane's half-wave of 32 lanes (0 when
-// every value is 0).
-__device__ __forceinline__ int half_exponent(float v) {
-  uint32_t u = __float_as_uint(v) & 0x7FFFFFFFu;
-  u = max(u, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)u, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
-  u = max(u, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)u, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
-  u = max(u, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)u, 0x141, 0xF, 0xF, false));  // row_half_mirror
-  u = max(u, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)u, 0x140, 0xF, 0xF, false));  // row_mirror
-  u = max(u, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)u, 0x142, 0xA, 0xF, false));  // row_bcast:15
-  const uint32_t m0 = (uint32_t)__builtin_amdgcn_readlane((int)u, 31);
-  const uint32_t m1 = (uint32_t)__builtin_amdgcn_readlane((int)u, 63);
-  const uint32_t m = (threadIdx.x & 32) ? m1 : m0;
-  return m ? (int)(m >> 23) - 127 : 0;
+// floor(log2 g) for a normal positive g (the gain G >= 1).
+__device__ __forceinline__ int gain_exp(float g) { return (int)(__float_as_uint(g) >> 23) - 127; }
+
+// Exclusive scan over the 64 lanes, in lane order, of the affine maps
+// c -> A c + B: the composition of the maps of lanes 0..l-1 (identity for lane
+// 0), as DPP row shifts and row broadcasts (identity where a lane has no
+// source).
+__device__ __forceinline__ float lane_carry(float A, float B) {
+  const int one = __float_as_int(1.0f);
+#define ZDT_STEP(CTRL, ROWMASK)                                                                    \
+  {                                                                                                \
+    const float pa = __int_as_float(__builtin_amdgcn_update_dpp(one, __float_as_int(A), CTRL, ROWMASK, 0xF, false)); \
+    const float pb = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(B), CTRL, ROWMASK, 0xF, false));   \
+    B = fmaf(A, pb, B);                                                                            \
+    A *= pa;                                                                                       \
+  }
+  ZDT_STEP(0x111, 0xF)  // row_shr:1
+  ZDT_STEP(0x112, 0xF)  // row_shr:2
+  ZDT_STEP(0x114, 0xF)  // row_shr:4
+  ZDT_STEP(0x118, 0xF)  // row_shr:8
+  ZDT_STEP(0x142, 0xA)  // row_bcast:15
+  ZDT_STEP(0x143, 0xC)  // row_bcast:31
+#undef ZDT_STEP
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(B), 0x138, 0xF, 0xF, false));  // wave_shr:1
+}
+
+// The L-then-R pass pair (or U-then-D) of one line of n values, run by one
+// whole wave: out = pair(in) with in = 1 everywhere when `in` is NULL; w[i] is
+// the forward weight into i (w[0] = w[n] = 0), the backward weight into i is
+// w[i + 1].  The line is cut into 64 blocks of ceil(n / 64) values; lane l
+// takes block l for the forward pass and block 63 - l for the backward one, so
+// both passes compose their block carries with the same forward lane scan.
+// `in` and `out` are LDS lines.
+__device__ void line_pair_gain(const float* in, float* out, const float* w, int n) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int m = (n + kWave - 1) / kWave;
+  int j0 = min(lane * m, n), j1 = min(j0 + m, n);
+  float ell = 0.0f, P = 1.0f;
+#pragma unroll 4
+  for (int j = j0; j < j1; ++j) {
+    ell = fmaf(w[j], ell, in ? in[j] : 1.0f);
+    P *= w[j];
+  }
+  float prev = lane_carry(P, ell);
+#pragma unroll 4
+  for (int j = j0; j < j1; ++j) {
+    prev = fmaf(w[j], prev, in ? in[j] : 1.0f);
+    out[j] = prev;
+  }
+  j0 = min((kWave - 1 - lane) * m, n);
+  j1 = min(j0 + m, n);
+  ell = 0.0f;
+  P = 1.0f;
+#pragma unroll 4
+  for (int j = j1 - 1; j >= j0; --j) {
+    ell = fmaf(w[j + 1], ell, out[j]);
+    P *= w[j + 1];
+  }
+  prev = lane_carry(P, ell);
+#pragma unroll 4
+  for (int j = j1 - 1; j >= j0; --j) {
+    prev = fmaf(w[j + 1], prev, out[j]);
+    out[j] = prev;
+  }
 }
 
 // H workgroups that hold the two halves of the same 128-byte lines (chunks 2p
@@ -470,7 +531,8 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
     a.right = jb.right;
     a.guide = jb.guide;
     a.vol = jb.vol;
-    a.ex = jb.ex;
+    a.g_in = jb.g_in;
+    a.g_out = jb.g_out;
   }
   constexpr int NW = 2 * R + 1;  // window side
   constexpr int N = NW * NW;
@@ -508,14 +570,11 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
   const HLayout lay = h_layout(kDT ? kWMax : W, R, LPS, SEG, kZncc, kDT, kHalf);
   if constexpr (kZncc) stage_zncc<R, LPS>(a, lay, smem, y, d0, MODE);
   if constexpr (kDT) stage_row_weights(a, (float*)(smem + lay.oWH), y);
+  float* GI = (float*)(smem + lay.oGI);
+  float* GO = (float*)(smem + lay.oGO);
   if constexpr (kHalf && MODE == kHPair) {
-    // exponents of the (one or two) 32-d chunks this workgroup's lanes hold
-    const int nck = (D + kExpChunk - 1) / kExpChunk;
-    int* XP = (int*)(smem + lay.oXP);
-    for (int h = 0; h < LPS / kExpChunk; ++h) {
-      const int8_t* er = a.ex + (size_t)y * W * nck + min(d0 / kExpChunk + h, nck - 1);
-      for (int x = threadIdx.x; x < W; x += blockDim.x) XP[h * (W + SEG) + x] = er[(size_t)x * nck];
-    }
+    const float* gr = a.g_in + (size_t)y * W;  // gains of the stored input row
+    for (int x = threadIdx.x; x < W; x += blockDim.x) GI[x] = gr[x];
   }
   __syncthreads();
 
@@ -581,9 +640,15 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
     float* EX2 = (float*)(smem + lay.oEX2);
     float* EXS2 = (float*)(smem + lay.oEXS2);
     constexpr bool scaled = kHalf;
-    const int nck = (D + kExpChunk - 1) / kExpChunk;
-    // this lane's exponents: row y, its 32-d chunk (written by lanes 0 and 32)
-    int8_t* exrow = scaled ? a.ex + (size_t)y * W * nck + min(d / kExpChunk, nck - 1) : nullptr;
+    if constexpr (scaled) {
+      // the row's gain after this pair, by the last wave; the other waves
+      // start their segments meanwhile and read it only after two barriers
+      if (wave == (int)(blockDim.x / kWave) - 1) {
+        line_pair_gain(MODE == kHPair ? GI : nullptr, GO, WH, W);
+        if (chunk == 0)
+          for (int x = lane; x < W; x += kWave) a.g_out[(size_t)y * W + x] = GO[x];
+      }
+    }
     const float* wp = WH + x0;  // W_L at x0 + k; padded past the row
     float c[SEG];
     // ---- loop A: values of the segment + carry-free L pass (ell) and weight product P
@@ -631,11 +696,11 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
 #pragma unroll
       for (int k = 0; k < SEG; ++k) c[k] = Elem<T>::bload(vrs, voff, step_soff(k));
       __builtin_amdgcn_sched_barrier(0);
-      const int* xp = (const int*)(smem + lay.oXP) + (LPS == 64 ? lane / kExpChunk : 0) * (W + SEG) + x0;
+      const float* gi = GI + x0;  // gains of the stored input at x0 + k
 #pragma unroll
       for (int k = 0; k < SEG; ++k) {
         const bool in = k < len;
-        if constexpr (scaled) c[k] = ldexpf(c[k], xp[k] - kExpBias);
+        if constexpr (scaled) c[k] = ldexpf(c[k], gain_exp(gi[k]) - kGainBias);
         const float w = wp[k];
         ell = in ? fmaf(w, ell, c[k]) : ell;
         P = in ? P * w : P;
@@ -679,14 +744,11 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
       next = in ? cr : next;
       step_fence(SEG - 1 - k, next);
     }
+    const float* go = GO + x0;  // gains of the output at x0 + k
 #pragma unroll
     for (int k = 0; k < SEG; ++k) {
       float v = c[k] * a.out_scale;
-      if (scaled && k < len) {  // scaled is a compile-time constant
-        const int e = half_exponent(active ? v : 0.0f);
-        v = ldexpf(v, kExpBias - e);
-        if ((lane & (kExpChunk - 1)) == 0 && active) exrow[(size_t)(x0 + k) * nck] = (int8_t)e;
-      }
+      if constexpr (scaled) v = ldexpf(v, kGainBias - gain_exp(go[k]));
       if (k < len && active) Elem<T>::bstore(vrs, voff, step_soff(k), v);
     }
   }
@@ -700,17 +762,20 @@ struct VArgs {
   int pitch, W, H, D;
   float inv_sigma_s, range_coef, out_scale;
   void* vol;
-  int8_t* ex;          // FP16 working volume exponent map (see above), else NULL
+  const float* g_in;   // FP16 working volume: gain map [H][W] of the stored input
+  float* g_out;        // and of the output (not for the WTA pass)
   int32_t* disp;       // WTA with a single chunk: final disparity
   float* part_val;     // WTA with several chunks: [chunk][H][W] minimum
   int32_t* part_idx;   // and its disparity
-  int segl, nw;
+  int segl, nseg;      // segment length and number of segments of a column
+  int nchunks;         // disparity chunks of LPS lanes
 };
 
 struct VJob {
   const uint8_t* guide;
   void* vol;
-  int8_t* ex;
+  const float* g_in;
+  float* g_out;
   int32_t* disp;
   float* part_val;
   int32_t* part_idx;
@@ -719,20 +784,40 @@ struct VJobs {
   VJob j[kMaxJobs];
 };
 
-// WV[H+1] (+ SEG spare entries), EX/EX2 [16*64*DPL], EXS/EXS2 [16], and for
-// scaled FP16 XP[2][H + SEG], the column's exponents per half-wave chunk
-__host__ __device__ inline int v_lds_words(int H, int SEG, int DPL, bool scaled) {
-  return (H + 1 + SEG) + 2 * (kMaxWaves * kWave * DPL + kMaxWaves) + (scaled ? 2 * (H + SEG) : 0);
+// WV[H+1] (+ SEG spare entries), EX/EX2 [32 segments x 32 lanes or 16 x 64],
+// EXS/EXS2 [kMaxSegs], and for the FP16 working volume GI, GO [H + SEG], the
+// column's gains before and after the pair.
+__host__ __device__ inline int v_lds_words(int H, int SEG, bool scaled) {
+  return (H + 1 + SEG) + 2 * (kMaxWaves * kWave + kMaxSegs) + (scaled ? 2 * (H + SEG) : 0);
 }
 
-__device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off));
-  return v;
+// Wave (LANES = 64) or half-wave (LANES = 32) minimum of B independent keys at
+// once; the result is in lane 63 (and lane 31 for the lower half-wave).
+template <int B, int LANES>
+__device__ __forceinline__ void group_min_u32(uint32_t (&m)[B]) {
+  if constexpr (LANES == 64) {
+    block_min_u32<B>(m);
+  } else {
+    const int id = -1;
+#define ZDT_STAGE(CTRL, ROWMASK)                                                                     \
+  _Pragma("unroll") for (int i = 0; i < B; ++i) m[i] =                                              \
+      min(m[i], (uint32_t)__builtin_amdgcn_update_dpp(id, (int)m[i], CTRL, ROWMASK, 0xF, false));
+    ZDT_STAGE(0xB1, 0xF)   // quad_perm [1,0,3,2]
+    ZDT_STAGE(0x4E, 0xF)   // quad_perm [2,3,0,1]
+    ZDT_STAGE(0x141, 0xF)  // row_half_mirror
+    ZDT_STAGE(0x140, 0xF)  // row_mirror
+    ZDT_STAGE(0x142, 0xA)  // row_bcast:15
+#undef ZDT_STAGE
+  }
 }
 
-// FULL: every wave's segment holds exactly SEG rows (checked by the host).
-template <int SEG, bool FULL, typename T, int DPL, bool WTA>
+// V pair (U then D, Eqs. DT3-DT4) of one column x and one chunk of LPS
+// disparities, optionally followed by the WTA.  A wave holds 64 / LPS segments
+// of the column, each LPS lanes wide (consecutive disparities).  FULL: every
+// segment holds exactly SEG rows (checked by the host; required for LPS = 32).
+// 16-bit volumes with LPS = 32 use the XCD-paired 1-D grid of the H pass, so
+// the two workgroups writing the halves of the same 128-byte lines share an L2.
+template <int SEG, bool FULL, typename T, int LPS, bool WTA>
 __global__ __launch_bounds__(1024) void vpass_kernel(VArgs args, VJobs jobs) {
   extern __shared__ uint32_t smem[];
   VArgs a = args;
@@ -740,175 +825,150 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs args, VJobs jobs) {
     const VJob& jb = jobs.j[blockIdx.z];
     a.guide = jb.guide;
     a.vol = jb.vol;
-    a.ex = jb.ex;
+    a.g_in = jb.g_in;
+    a.g_out = jb.g_out;
     a.disp = jb.disp;
     a.part_val = jb.part_val;
     a.part_idx = jb.part_idx;
   }
   constexpr bool kHalf = std::is_same<T, f16x>::value;  // exponent-scaled FP16
-  static_assert(DPL == 1 || !kHalf, "FP16 exponents are per half-wave chunk");
+  static_assert(LPS == 64 || (LPS == 32 && FULL), "two segments per wave need full segments");
+  constexpr int SPW = kWave / LPS;
   constexpr uint32_t kBytes = sizeof(T);
-  const int chunk = blockIdx.x, x = blockIdx.y;
-  const int d0 = chunk * kWave * DPL;
+  int chunk, x;
+  if constexpr (LPS == 32 && kBytes == 2) {
+    const HTile t = h_tile(blockIdx.x, a.W, a.nchunks);
+    if (t.y >= a.W || t.chunk >= a.nchunks) return;  // padding of the paired grid
+    x = t.y;
+    chunk = t.chunk;
+  } else {
+    chunk = blockIdx.x;
+    x = blockIdx.y;
+  }
+  const int d0 = chunk * LPS;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int dloc = lane & (LPS - 1);
+  const int seg = wave * SPW + (SPW == 1 ? 0 : lane / LPS);
+  const int d = d0 + dloc;
+  const bool act = d < a.D;
   const int W = a.W, H = a.H, D = a.D;
   float* WV = (float*)smem;
   float* EX = WV + (H + 1 + SEG);
-  float* EXS = EX + kMaxWaves * kWave * DPL;
-  float* EX2 = EXS + kMaxWaves;
-  float* EXS2 = EX2 + kMaxWaves * kWave * DPL;
-  int* XP = (int*)(EXS2 + kMaxWaves);
-  if constexpr (kHalf) {
-    // exponents of the column's two 32-d chunks (one per half-wave)
-    const int nck = (D + kExpChunk - 1) / kExpChunk;
-    for (int h = 0; h < 2; ++h) {
-      const int ck = min(chunk * 2 + h, nck - 1);  // a half-wave past D reads any valid chunk
-      for (int y = threadIdx.x; y < H; y += blockDim.x) XP[h * (H + SEG) + y] = a.ex[((size_t)y * W + x) * nck + ck];
-    }
-  }
+  float* EXS = EX + kMaxWaves * kWave;
+  float* EX2 = EXS + kMaxSegs;
+  float* EXS2 = EX2 + kMaxWaves * kWave;
+  float* GI = EXS2 + kMaxSegs;
+  float* GO = GI + (H + SEG);
+  if constexpr (kHalf)
+    for (int y = threadIdx.x; y < H; y += blockDim.x) GI[y] = a.g_in[(size_t)y * W + x];
   for (int y = threadIdx.x; y <= H; y += blockDim.x)
     WV[y] = (y >= 1 && y < H) ? dt_weight(a.guide[(size_t)y * a.pitch + x], a.guide[(size_t)(y - 1) * a.pitch + x],
                                           a.inv_sigma_s, a.range_coef)
                               : 0.0f;
   __syncthreads();
-  const int y0 = wave * a.segl;
-  const int len = FULL ? SEG : min(a.segl, H - y0);  // >= 1, wave-uniform
+  const int y0 = seg * a.segl;
+  const int len = FULL ? SEG : min(a.segl, H - y0);  // >= 1; wave-uniform
   const uint32_t rowbytes = (uint32_t)W * D * kBytes;
   // buffer over the volume from column x on; every offset below stays inside it
   const rsrc_t vrs = make_rsrc((const char*)a.vol + (size_t)x * D * kBytes,
                                (uint32_t)((size_t)H * W * D * kBytes - (size_t)x * D * kBytes));
   constexpr bool scaled = kHalf;
-  const int nck = (D + kExpChunk - 1) / kExpChunk;
-  const int* xp = XP + (lane / kExpChunk) * (H + SEG) + y0;  // this half-wave's exponents
-  auto yat = [&](int k) -> int { return y0 + (k < len ? k : len - 1); };
-  const float* wp = WV + y0;  // W_U at y0 + k; padded past the column
-  bool act[DPL];
-  uint32_t voff[DPL];
-#pragma unroll
-  for (int j = 0; j < DPL; ++j) {
-    const int dj = d0 + lane + kWave * j;
-    act[j] = dj < D;
-    voff[j] = (uint32_t)(act[j] ? dj : D - 1) * kBytes;
+  if constexpr (scaled && !WTA) {
+    // the column's gain after this pair, by the last wave (read after two barriers)
+    if (wave == (int)(blockDim.x / kWave) - 1) {
+      line_pair_gain(GI, GO, WV, H);
+      if (chunk == 0)
+        for (int y = lane; y < H; y += kWave) a.g_out[(size_t)y * W + x] = GO[y];
+    }
   }
+  const float* gi = GI + y0;  // gains of the stored input at y0 + k
+  const float* wp = WV + y0;  // W_U at y0 + k; padded past the column
+  // per-lane offset: the disparity, plus the segment's first row when the two
+  // halves of a wave hold different segments; per-step offset: the row step
+  const uint32_t voff = (uint32_t)(act ? d : D - 1) * kBytes + (SPW == 1 ? 0u : (uint32_t)y0 * rowbytes);
+  auto step_off = [&](int k) -> uint32_t {
+    if constexpr (SPW == 1) return (uint32_t)(y0 + (FULL || k < len ? k : len - 1)) * rowbytes;
+    return (uint32_t)k * rowbytes;
+  };
 
-  float c[DPL][SEG];
+  float c[SEG];
 #pragma unroll
-  for (int k = 0; k < SEG; ++k)
-#pragma unroll
-    for (int j = 0; j < DPL; ++j) c[j][k] = Elem<T>::bload(vrs, voff[j], (uint32_t)yat(k) * rowbytes);
+  for (int k = 0; k < SEG; ++k) c[k] = Elem<T>::bload(vrs, voff, step_off(k));
   __builtin_amdgcn_sched_barrier(0);
   // ---- loop A: carry-free U pass (decoding scaled FP16 values on the way)
-  float ell[DPL], P = 1.0f;
-#pragma unroll
-  for (int j = 0; j < DPL; ++j) ell[j] = 0.0f;
+  float ell = 0.0f, P = 1.0f;
 #pragma unroll
   for (int k = 0; k < SEG; ++k) {
     const bool in = k < len;
     const float w = wp[k];
-    if constexpr (scaled) c[0][k] = ldexpf(c[0][k], xp[k] - kExpBias);
-#pragma unroll
-    for (int j = 0; j < DPL; ++j) ell[j] = in ? fmaf(w, ell[j], c[j][k]) : ell[j];
+    if constexpr (scaled) c[k] = ldexpf(c[k], gain_exp(gi[k]) - kGainBias);
+    ell = in ? fmaf(w, ell, c[k]) : ell;
     P = in ? P * w : P;
-    if (k % kBlock == kBlock - 1) {
-#pragma unroll
-      for (int j = 0; j < DPL; ++j) pin(ell[j]);
-      pin(P);
-      fence();
-    }
+    step_fence(k, ell, P);
   }
-#pragma unroll
-  for (int j = 0; j < DPL; ++j) EX[(wave * DPL + j) * kWave + lane] = ell[j];
-  EXS[wave] = P;  // from every lane (see the H pass)
+  EX[seg * LPS + dloc] = ell;
+  EXS[seg] = P;  // from every lane (see the H pass)
   __syncthreads();
-  float prev[DPL];
-#pragma unroll
-  for (int j = 0; j < DPL; ++j) {  // at most 15 segments: a plain serial composition
-    float carry = 0.0f;
-    for (int s = 0; s < wave; ++s) carry = fmaf(EXS[s], carry, EX[(s * DPL + j) * kWave + lane]);
-    prev[j] = carry;
+  float prev;
+  if constexpr (SPW == 1) {  // at most 15 segments before: a plain serial composition
+    prev = 0.0f;
+    for (int s = 0; s < seg; ++s) prev = fmaf(EXS[s], prev, EX[s * LPS + dloc]);
+  } else {
+    prev = carry_in<false>(EX, EXS, seg, a.nseg, LPS, dloc, min(wave * SPW + SPW - 1, a.nseg - 1));
   }
   reload_fence();
   // ---- loop B: exact U pass; carry-free D value at y0
-  float acc[DPL], pi = 1.0f;
-#pragma unroll
-  for (int j = 0; j < DPL; ++j) acc[j] = 0.0f;
+  float acc = 0.0f, pi = 1.0f;
 #pragma unroll
   for (int k = 0; k < SEG; ++k) {
     const bool in = k < len;
     const float w = wp[k];
     if (k > 0) pi = in ? pi * w : pi;
-#pragma unroll
-    for (int j = 0; j < DPL; ++j) {
-      const float cu = fmaf(w, prev[j], c[j][k]);
-      c[j][k] = in ? cu : c[j][k];
-      prev[j] = in ? cu : prev[j];
-      acc[j] = in ? fmaf(cu, pi, acc[j]) : acc[j];
-    }
-    if (k % kBlock == kBlock - 1) {
-#pragma unroll
-      for (int j = 0; j < DPL; ++j) pin(prev[j], acc[j]);
-      pin(pi);
-      fence();
-    }
+    const float cu = fmaf(w, prev, c[k]);
+    c[k] = in ? cu : c[k];
+    prev = in ? cu : prev;
+    acc = in ? fmaf(cu, pi, acc) : acc;
+    step_fence(k, prev, acc, pi);
   }
   const float Q = pi * WV[y0 + len];
-#pragma unroll
-  for (int j = 0; j < DPL; ++j) EX2[(wave * DPL + j) * kWave + lane] = acc[j];
-  EXS2[wave] = Q;
+  EX2[seg * LPS + dloc] = acc;
+  EXS2[seg] = Q;
   __syncthreads();
-  float next[DPL];
-#pragma unroll
-  for (int j = 0; j < DPL; ++j) {
-    float kappa = 0.0f;
-    for (int s = a.nw - 1; s > wave; --s) kappa = fmaf(EXS2[s], kappa, EX2[(s * DPL + j) * kWave + lane]);
-    next[j] = kappa;
+  float next;
+  if constexpr (SPW == 1) {
+    next = 0.0f;
+    for (int s = a.nseg - 1; s > seg; --s) next = fmaf(EXS2[s], next, EX2[s * LPS + dloc]);
+  } else {
+    next = carry_in<true>(EX2, EXS2, seg, a.nseg, LPS, dloc, max(a.nseg - 1 - wave * SPW, 0));
   }
   reload_fence();
   // ---- loop D: exact D pass
 #pragma unroll
   for (int k = SEG - 1; k >= 0; --k) {
     const bool in = k < len;
-    const float w = wp[k + 1];
-#pragma unroll
-    for (int j = 0; j < DPL; ++j) {
-      const float cd = fmaf(w, next[j], c[j][k]);
-      c[j][k] = in ? cd : c[j][k];
-      next[j] = in ? cd : next[j];
-    }
-    if ((SEG - 1 - k) % kBlock == kBlock - 1) {
-#pragma unroll
-      for (int j = 0; j < DPL; ++j) pin(next[j]);
-      fence();
-    }
+    const float cd = fmaf(wp[k + 1], next, c[k]);
+    c[k] = in ? cd : c[k];
+    next = in ? cd : next;
+    step_fence(SEG - 1 - k, next);
   }
   if constexpr (!WTA) {
+    const float* go = GO + y0;  // gains of the output at y0 + k
 #pragma unroll
-    for (int j = 0; j < DPL; ++j) {
-      const int ck = chunk * 2 + lane / kExpChunk;  // this half-wave's 32-d chunk
-      int8_t* ex = scaled ? a.ex + (size_t)x * nck + min(ck, nck - 1) : nullptr;
-#pragma unroll
-      for (int k = 0; k < SEG; ++k)
-        if (k < len) {
-          float v = c[j][k] * a.out_scale;
-          if constexpr (scaled) {
-            const int e = half_exponent(act[j] ? v : 0.0f);
-            v = ldexpf(v, kExpBias - e);
-            if ((lane & (kExpChunk - 1)) == 0 && ck < nck) ex[(size_t)(y0 + k) * W * nck] = (int8_t)e;
-          }
-          if (act[j]) Elem<T>::bstore(vrs, voff[j], (uint32_t)(y0 + k) * rowbytes, v);
-        }
+    for (int k = 0; k < SEG; ++k) {
+      float v = c[k] * a.out_scale;
+      if constexpr (scaled) v = ldexpf(v, kGainBias - gain_exp(go[k]));
+      if (k < len && act) Elem<T>::bstore(vrs, voff, step_off(k), v);
     }
   } else {
     // argmin over the chunk's disparities, lowest d on ties (Eq. WTA1).  The
     // aggregated costs are >= 0, so their bit patterns order like the values
     // (|.| folds a -0 onto +0); idle lanes hold +inf.  Pixels are reduced 8 at
-    // a time with their DPP chains interleaved; pixel k's (argmin, minimum)
-    // is kept by lane k % 64 in result register k / 64, and the segment's
-    // results leave in one store per register.
-    static_assert(DPL == 1, "the fused WTA takes one disparity per lane");
+    // a time with their DPP chains interleaved; pixel k of a segment keeps its
+    // (argmin, minimum) in lane k % LPS of that segment's lanes, in result
+    // register k / LPS, and the results leave in one store per register.
     const uint32_t kInf = 0x7F800000u;
-    constexpr int NR = (SEG + kWave - 1) / kWave;
+    constexpr int NR = (SEG + LPS - 1) / LPS;
     constexpr int B = 8;
     int rd[NR];
     uint32_t rv[NR];
@@ -923,26 +983,37 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs args, VJobs jobs) {
 #pragma unroll
       for (int i = 0; i < B; ++i) {
         const int k = min(k0 + i, SEG - 1);
-        v[i] = act[0] ? (__float_as_uint(c[0][k]) & 0x7FFFFFFFu) : kInf;
+        v[i] = act ? (__float_as_uint(c[k]) & 0x7FFFFFFFu) : kInf;
         m[i] = v[i];
       }
-      block_min_u32<B>(m);
+      group_min_u32<B, LPS>(m);
 #pragma unroll
       for (int i = 0; i < B; ++i) {
         const int k = k0 + i;
         if (k < SEG && k < len) {
-          const uint32_t mk = (uint32_t)__builtin_amdgcn_readlane((int)m[i], 63);
-          const unsigned long long mask = __ballot(v[i] == mk);
-          const int db = d0 + (int)__builtin_ctzll(mask);
-          const bool mine = lane == k % kWave;
-          rd[k / kWave] = mine ? db : rd[k / kWave];
-          rv[k / kWave] = mine ? mk : rv[k / kWave];
+          const bool mine = dloc == k % LPS;
+          if constexpr (LPS == 64) {
+            const uint32_t mk = (uint32_t)__builtin_amdgcn_readlane((int)m[i], 63);
+            const unsigned long long mask = __ballot(v[i] == mk);
+            const int db = d0 + (int)__builtin_ctzll(mask);
+            rd[k / LPS] = mine ? db : rd[k / LPS];
+            rv[k / LPS] = mine ? mk : rv[k / LPS];
+          } else {
+            const uint32_t mk0 = (uint32_t)__builtin_amdgcn_readlane((int)m[i], 31);
+            const uint32_t mk1 = (uint32_t)__builtin_amdgcn_readlane((int)m[i], 63);
+            const uint32_t mk = lane < 32 ? mk0 : mk1;
+            const unsigned long long mask = __ballot(v[i] == mk);
+            const int db0 = d0 + (int)__builtin_ctz((uint32_t)mask);
+            const int db1 = d0 + (int)__builtin_ctz((uint32_t)(mask >> 32));
+            rd[k / LPS] = mine ? (lane < 32 ? db0 : db1) : rd[k / LPS];
+            rv[k / LPS] = mine ? mk : rv[k / LPS];
+          }
         }
       }
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      const int k = r * kWave + lane;
+      const int k = r * LPS + dloc;
       if (k < len) {
         const size_t p = (size_t)(y0 + k) * W + x;
         if (a.disp) {
@@ -979,6 +1050,12 @@ struct WJobs {
     }
   }
   jb.disp[p] = idx;
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off));
+  return v;
 }
 
 // Standalone WTA: each wave takes pixels p = global wave id, + total waves, ...

@@ -39,14 +39,15 @@ int launch(const char* name, Kernel kernel, dim3 grid, dim3 block, size_t lds, h
   return ZDT_OK;
 }
 
-// Segment lengths (values per lane) compiled for the H and V passes.  H pairs
-// give each wave two segments of 32 disparities when the row splits into full
-// segments (a 128-byte line per half-wave for FP32, half a line for 16-bit
-// volumes, whose two chunks then share an XCD), else one of 64 disparities.
+// Segment lengths (values per lane) compiled for the H and V passes.  A pass
+// gives each wave two segments of 32 disparities when the line splits into
+// full segments (a 128-byte line per half-wave for FP32, half a line for
+// 16-bit volumes, whose two chunks then share an XCD), else one of 64.
 constexpr int kHSegs32[] = {8, 20, 40, 60};  // LPS = 32: up to 32 segments per row
 constexpr int kHSegs64[] = {16, 40, 80};      // LPS = 64: up to 16 segments per row
-constexpr int kVSegs[] = {8, 12, 24, 48, 72};
-constexpr int kNumHSegs64 = 3, kNumVSegs = 5;
+constexpr int kVSegs[] = {8, 12, 24, 48, 72};  // 64 lanes: up to 16 segments per column
+constexpr int kVSegs32[] = {12, 24, 36};         // 32 lanes: up to 32 full segments per column
+constexpr int kNumHSegs64 = 3, kNumVSegs = 5, kNumVSegs32 = 3;
 // FP32 H pairs take two segments per wave when the row splits into an even
 // number (<= 32) of full segments of a compiled length; otherwise one.
 inline int h_full_seg32(int W) {
@@ -59,8 +60,7 @@ inline int h_full_seg32(int W) {
 #define ZDT_DECLARE_DISPATCH(SUFFIX)                                                                           \
   int dispatch_h_##SUFFIX(int mode, int R, int seg, int lps, const HArgs& a, const HJobs& jobs, int n,        \
                           hipStream_t s);                                                                     \
-  int dispatch_v_##SUFFIX(int seg, int dpl, bool wta, const VArgs& a, const VJobs& jobs, int n, int nchunks,   \
-                          hipStream_t s);                                                                     \
+  int dispatch_v_##SUFFIX(int seg, int lps, bool wta, const VArgs& a, const VJobs& jobs, int n, hipStream_t s); \
   int dispatch_wta_##SUFFIX(const void* vol, int npix, int D, int32_t* disp, hipStream_t s);
 ZDT_DECLARE_DISPATCH(f32)
 ZDT_DECLARE_DISPATCH(f16)

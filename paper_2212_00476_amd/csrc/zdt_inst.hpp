@@ -62,23 +62,42 @@ int run_h_radius(int R, int seg, const HArgs& a, const HJobs& jobs, int n, hipSt
   return fail(ZDT_EUNSUPPORTED, "no H-pass instance for radius %d", R);
 }
 
-template <int SEG, bool FULL, typename T, int DPL, bool WTA>
-int run_v(const VArgs& a, const VJobs& jobs, int n, int nchunks, hipStream_t s) {
-  return launch(WTA ? "dt_vpair_wta" : "dt_vpair", vpass_kernel<SEG, FULL, T, DPL, WTA>, dim3(nchunks, a.W, n),
-                dim3(kWave * a.nw), (size_t)v_lds_words(a.H, SEG, DPL, std::is_same<T, f16x>::value) * 4, s, a, jobs);
+template <int SEG, bool FULL, typename T, int LPS, bool WTA>
+int run_v(const VArgs& a, const VJobs& jobs, int n, hipStream_t s) {
+  VArgs b = a;
+  b.nchunks = (a.D + LPS - 1) / LPS;
+  dim3 grid(b.nchunks, a.W, n);
+  if constexpr (LPS == 32 && sizeof(T) == 2) {
+    // 1-D grid (per job) with the chunk pairs of a column on one XCD (see h_tile)
+    const int items = a.W * ((b.nchunks + 1) / 2);
+    grid = dim3((unsigned)((items + 7) / 8 * 16), 1, n);
+  }
+  const int nw = a.nseg / (kWave / LPS);
+  return launch(WTA ? "dt_vpair_wta" : "dt_vpair", vpass_kernel<SEG, FULL, T, LPS, WTA>, grid, dim3(kWave * nw),
+                (size_t)v_lds_words(a.H, SEG, std::is_same<T, f16x>::value) * 4, s, b, jobs);
 }
 
-template <typename T, int DPL, bool WTA>
-int run_v_seg(int seg, bool full, const VArgs& a, const VJobs& jobs, int n, int nchunks, hipStream_t s) {
-  switch (seg) {
-#define ZDT_CASE(SS)                                                       \
-  case SS:                                                                 \
-    return full ? run_v<SS, true, T, DPL, WTA>(a, jobs, n, nchunks, s)     \
-                : run_v<SS, false, T, DPL, WTA>(a, jobs, n, nchunks, s);
-    ZDT_CASE(8) ZDT_CASE(12) ZDT_CASE(24) ZDT_CASE(48) ZDT_CASE(72)
+template <typename T, bool WTA>
+int run_v_seg(int seg, int lps, bool full, const VArgs& a, const VJobs& jobs, int n, hipStream_t s) {
+  if (lps == 32) {
+    if (!full) return fail(ZDT_EUNSUPPORTED, "V pass: 32-lane segments must be full");
+    switch (seg) {
+#define ZDT_CASE(SS) \
+  case SS: return run_v<SS, true, T, 32, WTA>(a, jobs, n, s);
+      ZDT_CASE(12) ZDT_CASE(24) ZDT_CASE(36)
 #undef ZDT_CASE
+    }
+  } else {
+    switch (seg) {
+#define ZDT_CASE(SS)                                                  \
+  case SS:                                                            \
+    return full ? run_v<SS, true, T, 64, WTA>(a, jobs, n, s)          \
+                : run_v<SS, false, T, 64, WTA>(a, jobs, n, s);
+      ZDT_CASE(8) ZDT_CASE(12) ZDT_CASE(24) ZDT_CASE(48) ZDT_CASE(72)
+#undef ZDT_CASE
+    }
   }
-  return fail(ZDT_EUNSUPPORTED, "no V-pass instance for segment length %d", seg);
+  return fail(ZDT_EUNSUPPORTED, "no V-pass instance for segment length %d, %d lanes", seg, lps);
 }
 
 }  // namespace inst
@@ -113,13 +132,12 @@ int ZDT_CAT(dispatch_h_, ZDT_SUFFIX)(int mode, int R, int seg, int lps, const HA
   return fail(ZDT_EUNSUPPORTED, "no H-pass instance for mode %d, %d lanes per segment", mode, lps);
 }
 
-int ZDT_CAT(dispatch_v_, ZDT_SUFFIX)(int seg, int dpl, bool wta, const VArgs& a, const VJobs& jobs, int n,
-                                     int nchunks, hipStream_t s) {
+int ZDT_CAT(dispatch_v_, ZDT_SUFFIX)(int seg, int lps, bool wta, const VArgs& a, const VJobs& jobs, int n,
+                                     hipStream_t s) {
   using T = ZDT_ELEM;
-  if (dpl != 1) return fail(ZDT_EUNSUPPORTED, "V pass with %d disparities per lane", dpl);
-  const bool full = a.segl == seg && a.nw * seg == a.H;
-  if (!wta) return inst::run_v_seg<T, 1, false>(seg, full, a, jobs, n, nchunks, s);
-  return inst::run_v_seg<T, 1, true>(seg, full, a, jobs, n, nchunks, s);
+  const bool full = a.segl == seg && a.nseg * seg == a.H;
+  if (!wta) return inst::run_v_seg<T, false>(seg, lps, full, a, jobs, n, s);
+  return inst::run_v_seg<T, true>(seg, lps, full, a, jobs, n, s);
 }
 
 int ZDT_CAT(dispatch_wta_, ZDT_SUFFIX)(const void* vol, int npix, int D, int32_t* disp, hipStream_t s) {

@@ -159,7 +159,7 @@ Split h_split_stream(const zdt_params* p) {
 
 // ---- tile plans of the register-resident passes (zdt_plan in zdt.h)
 struct Plan {
-  int h_lanes, h_seg, v_seg;
+  int h_lanes, h_seg, v_lanes, v_seg;
 };
 
 bool in_list(int v, const int* list, int n) {
@@ -175,19 +175,28 @@ bool h_plan_ok(int W, int lanes, int seg) {
   return false;
 }
 
-bool v_plan_ok(int H, int seg) { return in_list(seg, kVSegs, kNumVSegs) && (H + seg - 1) / seg <= kMaxWaves; }
+bool v_plan_ok(int H, int lanes, int seg) {
+  if (lanes == 32)
+    return in_list(seg, kVSegs32, kNumVSegs32) && H % seg == 0 && (H / seg) % 2 == 0 && H / seg <= 2 * kMaxWaves;
+  if (lanes == 64) return in_list(seg, kVSegs, kNumVSegs) && (H + seg - 1) / seg <= kMaxWaves;
+  return false;
+}
 
 Split h_split_plan(int W, const Plan& pl) {
   if (pl.h_lanes == 32) return {pl.h_seg, pl.h_seg, W / pl.h_seg};
   return split_with(W, pl.h_seg);
 }
 
-Split v_split_plan(int H, const Plan& pl) { return split_with(H, pl.v_seg); }
+Split v_split_plan(int H, const Plan& pl) {
+  if (pl.v_lanes == 32) return {pl.v_seg, pl.v_seg, H / pl.v_seg};
+  return split_with(H, pl.v_seg);
+}
 
 // Default plan: two 32-lane segments per wave when the row splits into an even
-// number of full segments, else 64-lane segments; the shortest V segments
-// that cover the column with 8 waves (measured faster than 16 shorter ones:
-// fewer carries to compose, more workgroups per CU), else with 16.
+// number of full segments, else 64-lane segments; the shortest 64-lane V
+// segments that cover the column with 8 waves (measured faster than 16 shorter
+// ones: fewer carries to compose, more workgroups per CU), else with up to 16
+// waves (measured no slower than two 32-lane segments per wave at 1080 rows).
 Plan default_plan(const zdt_params* p) {
   Plan pl{};
   if (const int s32 = h_full_seg32(p->width)) {
@@ -197,6 +206,7 @@ Plan default_plan(const zdt_params* p) {
     pl.h_lanes = 64;
     pl.h_seg = split_line(p->width, kHSegs64, kNumHSegs64, kMaxWaves).seg;
   }
+  pl.v_lanes = 64;
   pl.v_seg = split_line(p->height, kVSegs, kNumVSegs, kMaxWaves / 2).seg;
   if (!pl.v_seg) pl.v_seg = split_line(p->height, kVSegs, kNumVSegs, kMaxWaves).seg;
   return pl;
@@ -215,18 +225,21 @@ std::vector<Plan> plan_candidates(const zdt_params* p) {
     if (h_plan_ok(W, 64, seg) && n0 != last) hs.push_back({64, seg});
     last = n0;
   }
-  std::vector<int> vs;
+  std::vector<std::pair<int, int>> vs;
+  for (int seg : kVSegs32)
+    if (v_plan_ok(H, 32, seg)) vs.push_back({32, seg});
   last = -1;
   for (int seg : kVSegs) {
     const int n0 = (H + seg - 1) / seg;
-    if (v_plan_ok(H, seg) && n0 != last) vs.push_back(seg);
+    if (v_plan_ok(H, 64, seg) && n0 != last) vs.push_back({64, seg});
     last = n0;
   }
   const Plan d = default_plan(p);
   std::vector<Plan> out{d};
   for (auto& h : hs)
-    for (int v : vs)
-      if (!(h.first == d.h_lanes && h.second == d.h_seg && v == d.v_seg)) out.push_back({h.first, h.second, v});
+    for (auto& v : vs)
+      if (!(h.first == d.h_lanes && h.second == d.h_seg && v.first == d.v_lanes && v.second == d.v_seg))
+        out.push_back({h.first, h.second, v.first, v.second});
   return out;
 }
 
@@ -319,14 +332,13 @@ int launch_v(const zdt_params* p, bool scaled, bool wta, VArgs a, const VJobs& t
              hipStream_t s) {
   const Split sp = v_split_plan(p->height, pl);
   a.segl = sp.segl;
-  a.nw = sp.nseg;
-  const int nchunks = (p->max_disp + kWave - 1) / kWave;
+  a.nseg = sp.nseg;
+  const int lps = pl.v_lanes;
   switch (p->vol_dtype) {
-    case ZDT_F32: return dispatch_v_f32(sp.seg, 1, wta, a, t, n, nchunks, s);
+    case ZDT_F32: return dispatch_v_f32(sp.seg, lps, wta, a, t, n, s);
     case ZDT_F16:
-      return scaled ? dispatch_v_f16x(sp.seg, 1, wta, a, t, n, nchunks, s)
-                    : dispatch_v_f16(sp.seg, 1, wta, a, t, n, nchunks, s);
-    case ZDT_BF16: return dispatch_v_bf16(sp.seg, 1, wta, a, t, n, nchunks, s);
+      return scaled ? dispatch_v_f16x(sp.seg, lps, wta, a, t, n, s) : dispatch_v_f16(sp.seg, lps, wta, a, t, n, s);
+    case ZDT_BF16: return dispatch_v_bf16(sp.seg, lps, wta, a, t, n, s);
   }
   return fail(ZDT_EINVAL, "bad dtype %d", p->vol_dtype);
 }
@@ -340,27 +352,30 @@ int dispatch_wta(int dtype, const void* vol, int npix, int D, int32_t* disp, hip
   return fail(ZDT_EINVAL, "bad dtype %d", dtype);
 }
 
-// Workspace of stereo_solve: the FP16 exponent map, then the WTA partial minima
-// of the disparity chunks (one V lane per disparity, 64-disparity chunks).
+// Workspace of stereo_solve: for FP16 working volumes two gain maps (the
+// H pairs write A, the V pairs write B), then the WTA partial minima of the
+// disparity chunks (one V lane per disparity; chunks of 32 or 64 disparities
+// depending on the plan, so the size covers 32).
 struct WsLayout {
-  size_t ex, part_val, part_idx, total;
+  size_t gain_a, gain_b, part_val, part_idx, total;
 };
 size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
-int wta_chunks(const zdt_params* p) { return (p->max_disp + kWave - 1) / kWave; }
+int wta_chunks(const zdt_params* p, int v_lanes) { return (p->max_disp + v_lanes - 1) / v_lanes; }
 WsLayout ws_layout(const zdt_params* p) {
   WsLayout L{};
   const size_t npix = (size_t)p->width * p->height;
-  const size_t nck = (size_t)(p->max_disp + kExpChunk - 1) / kExpChunk;
   size_t o = 0;
   if (p->vol_dtype == ZDT_F16 && p->dt_iters > 0) {
-    L.ex = o;
-    o += align256(npix * nck);
+    L.gain_a = o;
+    o += align256(npix * sizeof(float));
+    L.gain_b = o;
+    o += align256(npix * sizeof(float));
   }
-  if (p->dt_iters > 0 && wta_chunks(p) > 1) {
+  if (p->dt_iters > 0 && wta_chunks(p, 32) > 1) {
     L.part_val = o;
-    o += align256((size_t)wta_chunks(p) * npix * sizeof(float));
+    o += align256((size_t)wta_chunks(p, 32) * npix * sizeof(float));
     L.part_idx = o;
-    o += align256((size_t)wta_chunks(p) * npix * sizeof(int32_t));
+    o += align256((size_t)wta_chunks(p, 32) * npix * sizeof(int32_t));
   }
   L.total = o;
   return L;
@@ -382,7 +397,8 @@ int solve_group(const zdt_params* p, const JobPtrs* jobs, int n, hipStream_t s) 
   const Plan pl = plan_for(p);
   const WsLayout L = ws_layout(p);
   const bool scaled = p->vol_dtype == ZDT_F16;  // exponent-scaled FP16 working volume
-  const bool multi = wta_chunks(p) > 1;
+  const int vchunks = wta_chunks(p, pl.v_lanes);
+  const bool multi = vchunks > 1;
   const size_t npix = (size_t)p->width * p->height;
   HJobs ht{};
   VJobs vt{};
@@ -390,14 +406,15 @@ int solve_group(const zdt_params* p, const JobPtrs* jobs, int n, hipStream_t s) 
   for (int i = 0; i < n; ++i) {
     const JobPtrs& j = jobs[i];
     const uint8_t* guide = (p->flags & ZDT_FLAG_GUIDE_TARGET) ? j.right : j.left;
-    int8_t* ex = scaled ? (int8_t*)((char*)j.ws + L.ex) : nullptr;
+    float* ga = scaled ? (float*)((char*)j.ws + L.gain_a) : nullptr;
+    float* gb = scaled ? (float*)((char*)j.ws + L.gain_b) : nullptr;
     float* pv = multi ? (float*)((char*)j.ws + L.part_val) : nullptr;
     int32_t* pi = multi ? (int32_t*)((char*)j.ws + L.part_idx) : nullptr;
-    ht.j[i] = {j.left, j.right, guide, j.vol, ex};
-    vt.j[i] = {guide, j.vol, ex, multi ? nullptr : j.disp, pv, pi};
+    ht.j[i] = {j.left, j.right, guide, j.vol, gb, ga};                        // H pairs: B -> A
+    vt.j[i] = {guide, j.vol, ga, gb, multi ? nullptr : j.disp, pv, pi};      // V pairs: A -> B
     wt.j[i] = {pv, pi, j.disp};
   }
-  // An FP16 working volume keeps per-(pixel, chunk) exponents and needs no
+  // An FP16 working volume is scaled per pixel by its gain and needs no
   // global scale; the other types take the (1-K)-per-pass normalisation.
   const float sc = scaled ? 1.0f : pair_scale(p);
   const HArgs ha = make_hargs(p, sc);
@@ -412,7 +429,7 @@ int solve_group(const zdt_params* p, const JobPtrs* jobs, int n, hipStream_t s) 
   if (rc == ZDT_OK && multi) {
     const int threads = 256;
     rc = launch("wta_combine", wta_combine_kernel, dim3((unsigned)((npix + threads - 1) / threads), 1, n),
-                dim3(threads), 0, s, wt, wta_chunks(p), (int)npix);
+                dim3(threads), 0, s, wt, vchunks, (int)npix);
   }
   return rc;
 }
@@ -420,7 +437,7 @@ int solve_group(const zdt_params* p, const JobPtrs* jobs, int n, hipStream_t s) 
 // The raw-cost path (dt_iters = 0): streamed cost volume, then the WTA.
 int solve_raw(const zdt_params* p, const JobPtrs& j, hipStream_t s) {
   HJobs t{};
-  t.j[0] = {j.left, j.right, nullptr, j.vol, nullptr};
+  t.j[0] = {j.left, j.right, nullptr, j.vol, nullptr, nullptr};
   const Plan pl = plan_for(p);
   int rc = launch_h(p, p->vol_dtype, kCost, false, make_hargs(p, 1.0f), t, 1, pl, s);
   if (rc) return rc;
@@ -439,21 +456,21 @@ int check_job(const zdt_params* p, const uint8_t* left, const uint8_t* right, co
   return ZDT_OK;
 }
 
-zdt_plan to_c(const Plan& pl) { return zdt_plan{pl.h_lanes, pl.h_seg, pl.v_seg, 0}; }
+zdt_plan to_c(const Plan& pl) { return zdt_plan{pl.h_lanes, pl.h_seg, pl.v_lanes, pl.v_seg}; }
 
 // Plan cache file: one line per shape,
-//   zdt-plan W H D R dtype : h_lanes h_seg v_seg  (best_us)
+//   zdt-plan W H D R dtype : h_lanes h_seg v_lanes v_seg  (best_us)
 bool read_cached_plan(const char* path, const zdt_params* p, Plan* out) {
   FILE* f = std::fopen(path, "r");
   if (!f) return false;
   char line[256];
   bool found = false;
   while (std::fgets(line, sizeof line, f)) {
-    int W, H, D, R, dt, hl, hs, vs;
-    if (std::sscanf(line, "zdt-plan %d %d %d %d %d : %d %d %d", &W, &H, &D, &R, &dt, &hl, &hs, &vs) == 8 &&
+    int W, H, D, R, dt, hl, hs, vl, vs;
+    if (std::sscanf(line, "zdt-plan %d %d %d %d %d : %d %d %d %d", &W, &H, &D, &R, &dt, &hl, &hs, &vl, &vs) == 9 &&
         W == p->width && H == p->height && D == p->max_disp && R == p->radius && dt == p->vol_dtype &&
-        h_plan_ok(W, hl, hs) && v_plan_ok(H, vs)) {
-      *out = {hl, hs, vs};
+        h_plan_ok(W, hl, hs) && v_plan_ok(H, vl, vs)) {
+      *out = {hl, hs, vl, vs};
       found = true;  // the last matching line wins
     }
   }
@@ -483,7 +500,7 @@ int zncc_cost_volume(const zdt_params* p, const uint8_t* left, const uint8_t* ri
   if (rc) return rc;
   if (!left || !right || !cost) return fail(ZDT_EINVAL, "zncc_cost_volume: NULL image or volume pointer");
   HJobs t{};
-  t.j[0] = {left, right, nullptr, cost, nullptr};
+  t.j[0] = {left, right, nullptr, cost, nullptr, nullptr};
   return launch_h(p, p->vol_dtype, kCost, false, make_hargs(p, 1.0f), t, 1, plan_for(p), (hipStream_t)stream);
 }
 
@@ -499,7 +516,7 @@ int zncc_window_sums(const zdt_params* p, const uint8_t* left, const uint8_t* ri
   a.s_t = s_t;
   a.s_tt = s_tt;
   HJobs t{};
-  t.j[0] = {left, right, nullptr, nullptr, nullptr};
+  t.j[0] = {left, right, nullptr, nullptr, nullptr, nullptr};
   return launch_h(p, ZDT_F32, kSums, false, a, t, 1, plan_for(p), (hipStream_t)stream);
 }
 
@@ -511,9 +528,9 @@ int dt_aggregate(const zdt_params* p, const uint8_t* guide, void* cost, double* 
   const float sc = pair_scale(p);
   const Plan pl = plan_for(p);
   HJobs ht{};
-  ht.j[0] = {nullptr, nullptr, guide, cost, nullptr};
+  ht.j[0] = {nullptr, nullptr, guide, cost, nullptr, nullptr};
   VJobs vt{};
-  vt.j[0] = {guide, cost, nullptr, nullptr, nullptr, nullptr};
+  vt.j[0] = {guide, cost, nullptr, nullptr, nullptr, nullptr, nullptr};
   for (int it = 0; it < p->dt_iters; ++it) {
     if ((rc = launch_h(p, p->vol_dtype, kHPair, false, make_hargs(p, sc), ht, 1, pl, s))) return rc;
     if ((rc = launch_v(p, false, false, make_vargs(p, sc), vt, 1, pl, s))) return rc;
@@ -597,10 +614,10 @@ int zdt_set_plan(const zdt_params* p, const zdt_plan* plan) {
     g_plans.erase(plan_key(p));
     return ZDT_OK;
   }
-  if (plan->reserved != 0 || !h_plan_ok(p->width, plan->h_lanes, plan->h_seg) || !v_plan_ok(p->height, plan->v_seg))
-    return fail(ZDT_EINVAL, "zdt_set_plan: plan (%d, %d, %d) does not fit %dx%d", plan->h_lanes, plan->h_seg,
-                plan->v_seg, p->width, p->height);
-  g_plans[plan_key(p)] = {plan->h_lanes, plan->h_seg, plan->v_seg};
+  if (!h_plan_ok(p->width, plan->h_lanes, plan->h_seg) || !v_plan_ok(p->height, plan->v_lanes, plan->v_seg))
+    return fail(ZDT_EINVAL, "zdt_set_plan: plan (%d, %d, %d, %d) does not fit %dx%d", plan->h_lanes, plan->h_seg,
+                plan->v_lanes, plan->v_seg, p->width, p->height);
+  g_plans[plan_key(p)] = {plan->h_lanes, plan->h_seg, plan->v_lanes, plan->v_seg};
   return ZDT_OK;
 }
 
@@ -687,8 +704,8 @@ int zdt_autotune(const zdt_params* p, const char* cache_path, zdt_plan* chosen, 
   if (cache_path) {
     FILE* f = std::fopen(cache_path, "a");
     if (!f) return fail(ZDT_EINVAL, "zdt_autotune: cannot append to %s", cache_path);
-    std::fprintf(f, "zdt-plan %d %d %d %d %d : %d %d %d  (%.1f us)\n", p->width, p->height, p->max_disp, p->radius,
-                 p->vol_dtype, best.h_lanes, best.h_seg, best.v_seg, 1000.0 * best_ms / kReps);
+    std::fprintf(f, "zdt-plan %d %d %d %d %d : %d %d %d %d  (%.1f us)\n", p->width, p->height, p->max_disp,
+                 p->radius, p->vol_dtype, best.h_lanes, best.h_seg, best.v_lanes, best.v_seg, 1000.0 * best_ms / kReps);
     std::fclose(f);
   }
   return ZDT_OK;

@@ -96,7 +96,7 @@ def _near_tie_ok(disp, cagg):
     return slack, slack <= DT_REL * dmax
 
 
-PLAN_SHAPES = [(320, 96, 32, 4), (90, 200, 8, 2), (640, 48, 40, 3)]
+PLAN_SHAPES = [(320, 96, 32, 4), (90, 200, 8, 2), (640, 48, 40, 3), (64, 72, 100, 2)]
 
 
 @pytest.mark.parametrize("shape", PLAN_SHAPES, ids=["%dx%d_d%d_r%d" % s for s in PLAN_SHAPES])
@@ -119,19 +119,20 @@ def test_every_plan_matches_oracle_fp32(shape):
         zdt.set_plan(p, None)
 
 
-def test_every_plan_matches_oracle_fp16():
+@pytest.mark.parametrize("dtype", [zdt.ZDT_F16, zdt.ZDT_BF16], ids=["f16", "bf16"])
+def test_every_plan_matches_oracle_16bit(dtype):
     W, H, D, r = 320, 96, 32, 4
     pr = scenes.bands_pair()
     o_disp = oracle.stereo_solve(pr.left, pr.right, D, r, 20.0, 0.1, 3)
-    p = zdt.params(W, H, D, r, vol_dtype=zdt.ZDT_F16)
+    p = zdt.params(W, H, D, r, vol_dtype=dtype)
     L, R = dev(pr.left), dev(pr.right)
     try:
         for plan in zdt.plan_candidates(p):
             zdt.set_plan(p, plan)
             disp = zdt.Solver(p)(L, R).cpu().numpy()
             mism = (disp != o_disp).mean()
-            note(f"plan {plan}: FP16 mismatch {100 * mism:.4f} %")
-            assert mism <= 1e-3, plan
+            note(f"plan {plan}: dtype {dtype} mismatch {100 * mism:.4f} %")
+            assert mism <= (1e-3 if dtype == zdt.ZDT_F16 else 2e-2), plan
     finally:
         zdt.set_plan(p, None)
 
@@ -195,3 +196,27 @@ def test_autotune_pins_a_candidate_and_caches_it(tmp_path):
         assert cache.read_text() == text
     finally:
         zdt.set_plan(p, None)
+
+
+@pytest.mark.parametrize("shape", [(320, 96, 32, 4), (1280, 384, 128, 4), (100, 70, 40, 2)],
+                         ids=["320x96", "1280x384", "100x70"])
+def test_fp16_gain_maps_match_oracle(shape):
+    """The FP16 working volume is scaled per pixel by the DT gain G (the DT of
+    an all-ones slice).  After a 3-sweep solve the workspace's second gain map
+    holds G after two full sweeps (written by the second V pair); it must equal
+    the oracle's aggregation of ones within the DT bound.  (White-box: the map
+    sits at offset align256(W*H*4) of the workspace.)"""
+    W, H, D, r = shape
+    pr = pair_for(W, H, D, seed=5)
+    p = zdt.params(W, H, D, r, vol_dtype=zdt.ZDT_F16)
+    s = zdt.Solver(p)
+    s(dev(pr.left), dev(pr.right))
+    torch.cuda.synchronize()
+    off = (W * H * 4 + 255) // 256 * 256
+    g = s.ws[off:off + W * H * 4].view(torch.float32).reshape(H, W).cpu().numpy().astype(np.float64)
+    wh, wv = oracle.dt_weights(pr.left, 20.0, 0.1)
+    want = oracle.dt_aggregate(np.ones((H, W, 1)), wh, wv, 2)[:, :, 0]
+    rel = np.abs(g - want).max() / np.abs(want).max()
+    note(f"gain map after 2 sweeps: max rel err {rel:.2e}, range {want.min():.3g}..{want.max():.3g}")
+    assert np.isfinite(g).all() and (g >= 1.0).all()
+    assert rel <= DT_REL

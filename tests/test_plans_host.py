@@ -13,12 +13,16 @@ SHAPES = [(1280, 384, 128), (640, 192, 64), (1920, 1080, 256), (320, 96, 32), (9
 
 
 def _valid(W, H, plan):
-    lanes, hseg, vseg = plan
+    lanes, hseg, vlanes, vseg = plan
     if lanes == 32:
         h_ok = hseg in (8, 20, 40, 60) and W % hseg == 0 and (W // hseg) % 2 == 0 and W // hseg <= 32
     else:
         h_ok = lanes == 64 and hseg in (16, 40, 80) and -(-W // hseg) <= 16
-    return h_ok and vseg in (8, 12, 24, 48, 72) and -(-H // vseg) <= 16
+    if vlanes == 32:
+        v_ok = vseg in (12, 24, 36) and H % vseg == 0 and (H // vseg) % 2 == 0 and H // vseg <= 32
+    else:
+        v_ok = vlanes == 64 and vseg in (8, 12, 24, 48, 72) and -(-H // vseg) <= 16
+    return h_ok and v_ok
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=["%dx%d_d%d" % s for s in SHAPES])
@@ -34,11 +38,13 @@ def test_plan_candidates_are_valid_and_distinct(shape):
         assert c[0][0] == 32
 
 
-def test_known_candidates_1280x384():
+def test_known_candidates():
     p = zdt.params(1280, 384, 128)
-    assert zdt.plan_candidates(p)[0] == (32, 40, 48)   # 8 waves of 48 rows
-    assert set(zdt.plan_candidates(p)) == {(32, 40, 24), (32, 40, 48), (32, 40, 72), (64, 80, 24), (64, 80, 48),
-                                           (64, 80, 72)}
+    assert zdt.plan_candidates(p)[0] == (32, 40, 64, 48)   # 8 waves of 48 rows
+    v = {(32, 12), (32, 24), (64, 24), (64, 48), (64, 72)}   # 384 = 32 x 12 = 16 x 24
+    assert set(zdt.plan_candidates(p)) == {h + vv for h in ((32, 40), (64, 80)) for vv in v}
+    # 1080 rows: no 8-wave split; 15 waves of 72 by default, 30 half-waves of 36 as the other candidate
+    assert zdt.plan_candidates(zdt.params(1920, 1080, 256)) == [(32, 60, 64, 72), (32, 60, 32, 36)]
 
 
 def test_set_plan_round_trip_and_rejects_misfits():
@@ -50,7 +56,8 @@ def test_set_plan_round_trip_and_rejects_misfits():
         assert zdt.get_plan(p) == other
         # the plan is per shape and volume type: another dtype keeps its default
         assert zdt.get_plan(zdt.params(640, 192, 64)) == default
-        for bad in ((32, 60, 12), (64, 16, 12), (32, 20, 8), (48, 20, 12), (32, 20, 13)):
+        for bad in ((32, 60, 64, 12), (64, 16, 64, 12), (32, 20, 64, 8), (48, 20, 64, 12), (32, 20, 64, 13),
+                    (32, 20, 32, 36), (32, 20, 16, 12)):
             with pytest.raises(zdt.ZdtError) as e:
                 zdt.set_plan(p, bad)
             assert e.value.code == _lib.ZDT_EINVAL
@@ -62,12 +69,12 @@ def test_set_plan_round_trip_and_rejects_misfits():
 
 def test_autotune_takes_a_cached_plan_without_timing(tmp_path):
     p = zdt.params(640, 192, 64, vol_dtype=zdt.ZDT_F16)
-    want = (64, 40, 24)
+    want = (64, 40, 32, 24)
     cache = tmp_path / "plans.txt"
-    cache.write_text("zdt-plan 640 192 64 4 1 : 32 20 12  (1.0 us)\n"
-                     "zdt-plan 640 192 64 4 0 : 32 40 48  (1.0 us)\n"   # other dtype
-                     "zdt-plan 640 192 64 4 1 : 64 40 24  (0.9 us)\n"   # the last match wins
-                     "zdt-plan 640 192 64 4 1 : 32 60 12  (0.1 us)\n")  # does not fit: ignored
+    cache.write_text("zdt-plan 640 192 64 4 1 : 32 20 64 12  (1.0 us)\n"
+                     "zdt-plan 640 192 64 4 0 : 32 40 64 48  (1.0 us)\n"   # other dtype
+                     "zdt-plan 640 192 64 4 1 : 64 40 32 24  (0.9 us)\n"   # the last match wins
+                     "zdt-plan 640 192 64 4 1 : 32 60 64 12  (0.1 us)\n")  # does not fit: ignored
     try:
         got = zdt.autotune(p, str(cache), stream=0)
         assert got == want and zdt.get_plan(p) == want

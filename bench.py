@@ -199,6 +199,32 @@ def main():
         forms[name] = {"ms_per_step": round(ms, 5), "gcost_evals_per_s": round(nvol / (ms * 1e-3) / 1e9, 3),
                        "fps": round(1000.0 / ms, 1)}
 
+    # the paper's own system parameters: 3x3 window, one sweep, sigma_s = 5,
+    # sigma_r = 52 on 0..255 (the configuration of its 32 fps Jetson TX2 figure)
+    for name, dt in (("paper_cfg_f32", zdt.ZDT_F32), ("paper_cfg_f16", zdt.ZDT_F16)):
+        p = zdt.params(W, H, D, 1, 5.0, 52.0 / 255.0, 1, vol_dtype=dt)
+        solver = zdt.Solver(p, device=dev)
+        disp = torch.empty((H, W), dtype=torch.int32, device=dev)
+        ms = time_steps(lambda: solver(L, Rt, disp), args.steps, args.warmup, torch)
+        forms[name] = {"ms_per_step": round(ms, 5), "gcost_evals_per_s": round(nvol / (ms * 1e-3) / 1e9, 3),
+                       "fps": round(1000.0 / ms, 1), "window": 3, "dt_iters": 1, "sigma_s": 5.0,
+                       "sigma_r": round(52.0 / 255.0, 6)}
+        del solver
+
+    # window / disparity sweep of the cost volume alone (sides 3..15, D = 96 and
+    # 128; the shape of the paper's ZNCC timing comparison): the sliding-window
+    # cross term keeps the cost nearly independent of the window side
+    sweep = {}
+    for dd in (96, 128):
+        row = {}
+        for side in range(3, 17, 2):
+            p = zdt.params(W, H, dd, side // 2)
+            vol_s = torch.empty((H, W, dd), dtype=torch.float32, device=dev)
+            ms = time_steps(lambda: zdt.zncc_cost_volume(p, L, Rt, vol_s), max(10, args.steps // 10), 3, torch)
+            row[str(side)] = round(ms, 4)
+            del vol_s
+        sweep["D%d" % dd] = row
+
     # the plain FP32 per-pair form: raw cost volume, 12 unfused DT passes, WTA
     p32 = zdt.params(W, H, D, R, SIGMA_S, SIGMA_R, ITERS)
     vol = torch.empty((H, W, D), dtype=torch.float32, device=dev)
@@ -264,6 +290,7 @@ def main():
         "kernels_bf16": kernels_bf16, "roofline": roofline, "cpu_baseline": cpu,
         "p99_ms_served": served["poisson"]["p99_ms"] if served else None,
         "batch": batch, "serving": served,
+        "window_sweep_cost_ms": sweep,
     }
     print(json.dumps(line))
 

@@ -55,7 +55,7 @@ typedef struct zdt_params {
   int32_t height;       /* H >= 1                                                      */
   int32_t pitch;        /* bytes between image rows, >= W                              */
   int32_t max_disp;     /* D >= 1; candidates d = 0 .. D-1                             */
-  int32_t radius;       /* r, window side l = 2r+1; 0 <= r <= 6 (int32-exact sums)     */
+  int32_t radius;       /* r, window side l = 2r+1; 0 <= r <= 7 (32-bit exact sums)     */
   float sigma_s;        /* DT spatial parameter, > 0 (Eq. a: a = K = exp(-1/sigma_s))  */
   float sigma_r;        /* DT range parameter in intensity/255 units, > 0; +inf turns  */
                         /* the range term off                                          */
@@ -175,7 +175,7 @@ int zdt_autotune(const zdt_params* params, const char* cache_path, zdt_plan* cho
  *   s_t, s_tt      [H][W+D-1]    sum of I_T and I_T^2 over the window at x',
  *                                x' = -(D-1) .. W-1 stored at index x'+D-1
  *   s_rt           [H][W][D]     sum over the window of I_R(x+i,y+j) I_T(x-d+i,y+j)
- * All int32 (exact: l <= 13 keeps every sum below 2^31). */
+ * All int32 and exact (every sum is below 2^31 for l <= 15). */
 int zncc_window_sums(const zdt_params* params, const uint8_t* left, const uint8_t* right, int32_t* s_l,
                      int32_t* s_ll, int32_t* s_t, int32_t* s_tt, int32_t* s_rt, void* stream);
 

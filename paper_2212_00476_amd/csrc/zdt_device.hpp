@@ -370,6 +370,8 @@ __device__ __forceinline__ uint32_t colsum(const uint32_t* LP, const uint32_t* T
 }
 
 // cost = 1 - clamp(ZNCC, -1, 1) from the exact integer numerator l^2 S_RT - S_R S_T.
+// Both products stay below 2^32 for l <= 15 and the difference is below 2^31
+// in magnitude, so the wrapping 32-bit subtraction is exact.
 __device__ __forceinline__ float zncc_cost_from(uint32_t srt, int sl, float il, int st, float it, int N) {
   const int num = (int)(__umul24((uint32_t)N, srt) - __umul24((uint32_t)sl, (uint32_t)st));
   const float c = fmaf(-(float)num, il * it, 1.0f);

@@ -56,7 +56,7 @@ int run_h_radius(int R, int seg, const HArgs& a, const HJobs& jobs, int n, hipSt
   case RR:                                                          \
     if constexpr (stream) return run_h<RR, 0, 64, T, MODE>(a, jobs, n, s); \
     else return run_h_seg<RR, LPS, T, MODE>(seg, a, jobs, n, s);
-    ZDT_CASE(0) ZDT_CASE(1) ZDT_CASE(2) ZDT_CASE(3) ZDT_CASE(4) ZDT_CASE(5) ZDT_CASE(6)
+    ZDT_CASE(0) ZDT_CASE(1) ZDT_CASE(2) ZDT_CASE(3) ZDT_CASE(4) ZDT_CASE(5) ZDT_CASE(6) ZDT_CASE(7)
 #undef ZDT_CASE
   }
   return fail(ZDT_EUNSUPPORTED, "no H-pass instance for radius %d", R);

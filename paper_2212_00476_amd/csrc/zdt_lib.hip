@@ -98,7 +98,10 @@ using namespace zdt;
 
 namespace {
 
-constexpr int kMaxRadius = 6;
+// l = 2r + 1 <= 15: every window sum stays below 2^32 and each cost numerator
+// l^2 S_RT - S_R S_T, whose magnitude is at most l^4 * 127.5^2 < 2^31, is exact
+// when formed in wrapping 32-bit arithmetic.
+constexpr int kMaxRadius = 7;
 
 size_t dtype_size(int t) { return t == ZDT_F32 ? 4 : 2; }
 
@@ -109,7 +112,7 @@ int check_params(const zdt_params* p, const char* who) {
   if (p->max_disp < 1) return fail(ZDT_EINVAL, "%s: max_disp must be >= 1", who);
   if (p->radius < 0) return fail(ZDT_EINVAL, "%s: radius must be >= 0", who);
   if (p->radius > kMaxRadius)
-    return fail(ZDT_EUNSUPPORTED, "%s: radius %d > %d (int32 sums need l <= 13)", who, p->radius, kMaxRadius);
+    return fail(ZDT_EUNSUPPORTED, "%s: radius %d > %d (32-bit exact sums need l <= 15)", who, p->radius, kMaxRadius);
   if (!(p->sigma_s > 0.0f) || std::isinf(p->sigma_s))
     return fail(ZDT_EINVAL, "%s: sigma_s must be finite and > 0", who);
   if (!(p->sigma_r > 0.0f)) return fail(ZDT_EINVAL, "%s: sigma_r must be > 0 (or +inf)", who);

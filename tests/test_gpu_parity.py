@@ -50,7 +50,7 @@ def pair_for(W, H, D, seed=0):
 # (W, H, D, r): config-0 shape, ragged sizes, D not a multiple of 64, D = 1,
 # D > W, image smaller than the window, r = 0, r = 6, the widest row.
 SHAPES = [(320, 96, 32, 4), (37, 23, 11, 2), (100, 17, 65, 3), (50, 40, 1, 1), (30, 12, 45, 4), (7, 5, 9, 4),
-          (129, 33, 130, 0), (640, 24, 20, 6), (1280, 9, 16, 5), (333, 70, 64, 1)]
+          (129, 33, 130, 0), (640, 24, 20, 6), (1280, 9, 16, 5), (333, 70, 64, 1), (100, 40, 20, 7)]
 
 
 def ids(shapes):
@@ -261,7 +261,7 @@ def test_stereo_solve_bands(dtype):
 
 
 ODD = [(37, 23, 11, 2), (100, 17, 65, 3), (50, 40, 1, 1), (30, 12, 45, 4), (7, 5, 9, 4), (129, 33, 130, 0),
-       (200, 150, 200, 2), (64, 700, 16, 3)]
+       (200, 150, 200, 2), (64, 700, 16, 3), (120, 50, 30, 7)]
 
 
 @pytest.mark.parametrize("iters", [0, 1, 2])
@@ -409,3 +409,57 @@ def test_full_size_dt_slices_fp32():
     rel = _dt_check(got, full["cagg"])
     note(f"  max rel err = {rel:.3e}")
     assert rel <= DT_REL
+
+
+# ------------------------------------------------ the paper's own configuration
+PAPER = dict(r=1, sigma_s=5.0, sigma_r=52.0 / 255.0, iters=1)   # 3x3, one sweep, sigma_r = 52 on 0..255
+
+
+@pytest.mark.parametrize("dtype", [zdt.ZDT_F32, zdt.ZDT_F16, zdt.ZDT_BF16], ids=["f32", "f16", "bf16"])
+def test_paper_configuration_full_size(dtype):
+    """1280x384, D = 128 with the paper's system parameters (3x3 ZNCC, one
+    L-R-U-D sweep, sigma_s = 5, sigma_r = 52 in raw intensity units): FP32
+    disagreements are near-ties of the FP64 oracle; 16-bit within 0.1 % / 2 %."""
+    W, H, D = 1280, 384, 128
+    pr = scenes.workload("planes_1280x384_d128")
+    if "paper" not in _FULL:
+        note(f"oracle: 128 slices at the paper's parameters on {ORACLE_THREADS} threads")
+        c = oracle.solve_slices(pr.left, pr.right, PAPER["r"], range(D), PAPER["sigma_s"], PAPER["sigma_r"],
+                                PAPER["iters"], threads=ORACLE_THREADS)
+        _FULL["paper"] = np.ascontiguousarray(np.moveaxis(c, 0, 2))
+    cagg = _FULL["paper"]
+    o_disp = np.argmin(cagg, axis=2)
+    p = zdt.params(W, H, D, PAPER["r"], PAPER["sigma_s"], PAPER["sigma_r"], PAPER["iters"], vol_dtype=dtype)
+    disp = zdt.Solver(p)(dev(pr.left), dev(pr.right)).cpu().numpy()
+    mism = (disp != o_disp).mean()
+    note(f"  paper configuration dtype={dtype}: mismatch {100 * mism:.4f} %")
+    if dtype == zdt.ZDT_F32:
+        slack, ok = _near_tie_ok(disp, cagg)
+        assert ok.all(), slack[~ok].max()
+    else:
+        assert mism <= (1e-3 if dtype == zdt.ZDT_F16 else 2e-2)
+
+
+def test_cost_bright_15x15_window_wraps_exactly():
+    """l = 15 on bright textured images: l^2 S_RT exceeds 2^31 (up to 3.3e9),
+    so the numerator is formed in wrapping 32-bit arithmetic; sums stay
+    bit-exact and costs match the oracle's int64 / FP64 evaluation."""
+    W, H, D, r = 90, 40, 24, 7
+    rng = np.random.default_rng(15)
+    left = rng.integers(190, 256, (H, W)).astype(np.uint8)
+    left[rng.random((H, W)) < 0.05] = 0                        # a few dark pixels keep the variance up
+    right = np.roll(np.clip(left.astype(np.int32) - 3, 0, 255).astype(np.uint8), -4, axis=1)   # match at d = 4
+    p = zdt.params(W, H, D, r)
+    i32 = dict(dtype=torch.int32, device="cuda")
+    s_rt = torch.empty((H, W, D), **i32)
+    zdt.zncc_window_sums(p, dev(left), dev(right), s_rt=s_rt)
+    cost = torch.empty((H, W, D), dtype=torch.float32, device="cuda")
+    zdt.zncc_cost_volume(p, dev(left), dev(right), cost)
+    torch.cuda.synchronize()
+    srt = host(s_rt)
+    assert int(srt.max()) * (2 * r + 1) ** 2 > 2 ** 31           # the case is really past int32
+    assert np.array_equal(srt, oracle.cross_sums(left, right, D, r))
+    want = oracle.zncc_cost(left, right, D, r)
+    err = np.abs(host(cost).astype(np.float64) - want).max()
+    note(f"  l=15 bright: max |d cost| = {err:.2e}")
+    assert err <= 1e-5

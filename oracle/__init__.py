@@ -57,6 +57,10 @@ def _load():
         lib.oracle_dt_aggregate.argtypes = [P, I, I, I, P, P, I]
         lib.oracle_wta.argtypes = [P, I, I, I, P]
         lib.oracle_stereo_solve.argtypes = [P, P, I, I, I, I, I, Dbl, Dbl, I, I, P, P]
+        lib.oracle_i8_encode.argtypes = [ctypes.c_int16]
+        lib.oracle_i8_encode.restype = ctypes.c_uint8
+        lib.oracle_i8_decode.argtypes = [ctypes.c_uint8]
+        lib.oracle_i8_decode.restype = ctypes.c_int16
         for f in ("oracle_window_sums", "oracle_cross_sums", "oracle_zncc_cost_slice", "oracle_zncc_cost",
                   "oracle_dt_weights", "oracle_dt_slice", "oracle_dt_aggregate", "oracle_wta",
                   "oracle_stereo_solve"):
@@ -209,3 +213,17 @@ def solve_slices(left, right, r, ds, sigma_s, sigma_r, iters, guide_target=False
         with ThreadPoolExecutor(max_workers=threads) as ex:
             list(ex.map(one, range(len(ds))))
     return out
+
+
+def i8_encode(values):
+    """The 8-bit codes (Sec. IV-C) of int16 values, elementwise."""
+    lib = _load()
+    v = np.asarray(values, np.int16)
+    return np.array([lib.oracle_i8_encode(int(x)) for x in v.ravel()], np.uint8).reshape(v.shape)
+
+
+def i8_decode(codes):
+    """The int16 values of 8-bit codes (Sec. IV-C), elementwise."""
+    lib = _load()
+    c = np.asarray(codes, np.uint8)
+    return np.array([lib.oracle_i8_decode(int(x)) for x in c.ravel()], np.int16).reshape(c.shape)

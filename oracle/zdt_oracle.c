@@ -266,3 +266,34 @@ int oracle_stereo_solve(const uint8_t* L, const uint8_t* R, int pitch, int W, in
   if (!cost_agg_hwd) free(vol);
   return rc;
 }
+
+/* ---------------------------------------------------------------------------
+ * 8-bit code of a normalised 16-bit cost (Sec. IV-C, data encoding and
+ * decoding).  Only negative values carry information.  Of a negative value's
+ * bits 14..0, six significant bits below its leading run of ones are kept,
+ * with a 2-bit flag naming where they sit:
+ *   flag 01: bits 14..9, when bits 14..11 are not all ones;
+ *   flag 10: bits 10..5, when bits 14..11 are all ones but 10..7 are not;
+ *   flag 11: bits 6..1,  when bits 14..7 are all ones.
+ * The code is (six bits) << 2 | flag.  Reading for non-negative values: they
+ * encode to the all-zero byte (taking the steps literally, 0 would get flag
+ * 01 and decode to -32768).  Decoding: 0 gives 0; otherwise the six bits go
+ * back to their position, every bit above them (through bit 15) is set and
+ * every bit below is cleared.  A non-zero code with flag 00 is never produced
+ * and decodes to 0.
+ */
+uint8_t oracle_i8_encode(int16_t v) {
+  if (v >= 0) return 0;
+  const unsigned u = (uint16_t)v;
+  if (((u >> 11) & 0xFu) != 0xFu) return (uint8_t)((((u >> 9) & 0x3Fu) << 2) | 1u);
+  if (((u >> 7) & 0xFu) != 0xFu) return (uint8_t)((((u >> 5) & 0x3Fu) << 2) | 2u);
+  return (uint8_t)((((u >> 1) & 0x3Fu) << 2) | 3u);
+}
+
+int16_t oracle_i8_decode(uint8_t c) {
+  const unsigned flag = c & 3u, six = c >> 2;
+  if (c == 0 || flag == 0) return 0;
+  const int pos = flag == 1 ? 9 : (flag == 2 ? 5 : 1); /* lowest bit of the six */
+  const unsigned above = (0xFFFFu << (pos + 6)) & 0xFFFFu;
+  return (int16_t)(uint16_t)(above | (six << pos));
+}

@@ -275,3 +275,36 @@ def test_band_scene_exact_recovery():
         assert np.all(disp0[r:-r, xs] == d), k
         q = (hi - lo) // 4
         assert np.all(disp3[:, max(lo + q, d + r):hi - q] == d), k
+
+
+# ------------------------------------------------ 8-bit cost code (Sec. IV-C)
+def test_i8_codec_against_closed_form():
+    """Exhaustive over every int16: non-negative values code to 0; a negative
+    value decodes to itself with its low s bits cleared, s = 9 below -2048,
+    5 on [-2048, -128) and 1 on [-128, 0) -- the three flag positions stated
+    as value ranges instead of bit tests."""
+    v = np.arange(-32768, 32768, dtype=np.int64)
+    codes = oracle.i8_encode(v.astype(np.int16))
+    dec = oracle.i8_decode(codes).astype(np.int64)
+    assert np.all((codes == 0) == (v >= 0))
+    assert np.all(dec[v >= 0] == 0)
+    neg = v < 0
+    s = np.where(v < -2048, 9, np.where(v < -128, 5, 1))
+    want = v & ~((np.int64(1) << s) - 1)
+    assert np.array_equal(dec[neg], want[neg])
+    err = v[neg] - dec[neg]
+    assert np.all(err >= 0) and np.all(err < (np.int64(1) << s[neg]))
+    assert np.all(np.diff(dec[neg]) >= 0)                       # monotone
+    flags = codes[neg] & 3
+    assert set(np.unique(flags)) == {1, 2, 3}
+    assert np.array_equal(flags, np.where(v[neg] < -2048, 1, np.where(v[neg] < -128, 2, 3)))
+
+
+def test_i8_codec_round_trip_and_special_values():
+    produced = np.unique(oracle.i8_encode(np.arange(-32768, 32768).astype(np.int16)))
+    assert np.array_equal(oracle.i8_encode(oracle.i8_decode(produced)), produced)   # codes are fixed points
+    assert int(oracle.i8_encode(np.int16(-32768))) == 0x01 and int(oracle.i8_decode(np.uint8(0x01))) == -32768
+    assert int(oracle.i8_encode(np.int16(-1))) == 0xFF and int(oracle.i8_decode(np.uint8(0xFF))) == -2
+    assert int(oracle.i8_decode(np.uint8(0))) == 0
+    # codes with flag 00 are never produced
+    assert not np.any((produced != 0) & ((produced & 3) == 0))

@@ -201,7 +201,11 @@ def main():
 
     # the paper's own system parameters: 3x3 window, one sweep, sigma_s = 5,
     # sigma_r = 52 on 0..255 (the configuration of its 32 fps Jetson TX2 figure)
-    for name, dt in (("paper_cfg_f32", zdt.ZDT_F32), ("paper_cfg_f16", zdt.ZDT_F16)):
+    # (plus its Int16 / Int8 narrow volumes, T = 21, d_arb = 0; their
+    # disparities are compared with this FP32 form's)
+    paper_ref = None
+    for name, dt in (("paper_cfg_f32", zdt.ZDT_F32), ("paper_cfg_f16", zdt.ZDT_F16), ("paper_cfg_i16", zdt.ZDT_I16),
+                     ("paper_cfg_i8", zdt.ZDT_I8)):
         p = zdt.params(W, H, D, 1, 5.0, 52.0 / 255.0, 1, vol_dtype=dt)
         solver = zdt.Solver(p, device=dev)
         disp = torch.empty((H, W), dtype=torch.int32, device=dev)
@@ -209,6 +213,10 @@ def main():
         forms[name] = {"ms_per_step": round(ms, 5), "gcost_evals_per_s": round(nvol / (ms * 1e-3) / 1e9, 3),
                        "fps": round(1000.0 / ms, 1), "window": 3, "dt_iters": 1, "sigma_s": 5.0,
                        "sigma_r": round(52.0 / 255.0, 6)}
+        if paper_ref is None:
+            paper_ref = disp.clone()
+        else:
+            forms[name]["disagreement_vs_f32"] = round(float((disp != paper_ref).float().mean()), 6)
         del solver
 
     # window / disparity sweep of the cost volume alone (sides 3..15, D = 96 and

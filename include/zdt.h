@@ -44,7 +44,15 @@ typedef enum zdt_status {
   ZDT_EUNSUPPORTED = -4     /* valid, but outside what this build supports  */
 } zdt_status;
 
-typedef enum zdt_dtype { ZDT_F32 = 0, ZDT_F16 = 1, ZDT_BF16 = 2 } zdt_dtype;
+/* Volume element types.  ZDT_I16 and ZDT_I8 are the paper's narrow integer
+ * volumes (Sec. IV-C): the cost, made nearly zero-mean by subtracting the raw
+ * cost at d_arb = 0 before the first DT pass (Eq. DT_new), times T = 21,
+ * rounded to a saturated int16; ZDT_I8 stores that int16's 8-bit code (six
+ * significant bits plus a 2-bit position flag; only negative values are kept,
+ * non-negative ones code to 0), four codes per 32-bit word along d.  They are
+ * approximations for bandwidth (accuracy is reported, not bounded, against
+ * the exact aggregation); the recursions still run in float32. */
+typedef enum zdt_dtype { ZDT_F32 = 0, ZDT_F16 = 1, ZDT_BF16 = 2, ZDT_I16 = 3, ZDT_I8 = 4 } zdt_dtype;
 
 /* flags */
 #define ZDT_FLAG_NORMALIZE 1     /* scale each DT pass by (1 - K); forced for F16/BF16 */
@@ -178,6 +186,11 @@ int zdt_autotune(const zdt_params* params, const char* cache_path, zdt_plan* cho
  * All int32 and exact (every sum is below 2^31 for l <= 15). */
 int zncc_window_sums(const zdt_params* params, const uint8_t* left, const uint8_t* right, int32_t* s_l,
                      int32_t* s_ll, int32_t* s_t, int32_t* s_tt, int32_t* s_rt, void* stream);
+
+/* Test entry for the 8-bit code of ZDT_I8 volumes (Sec. IV-C, data encoding
+ * and decoding): codes[i] = encode(values[i]) and decoded[i] =
+ * decode(codes[i]) for i < n, on the device.  All three are DEVICE arrays. */
+int zdt_i8_codec(const int16_t* values, uint8_t* codes, int16_t* decoded, int64_t n, void* stream);
 
 /* Message for the calling thread's last non-OK return ("" if none). */
 const char* zdt_last_error(void);

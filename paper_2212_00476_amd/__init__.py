@@ -11,12 +11,14 @@ the tests and the benchmark.  PyTorch provides device memory and streams only.
 """
 from __future__ import annotations
 
-from ._lib import (ZDT_BF16, ZDT_F16, ZDT_F32, ZDT_FLAG_GUIDE_TARGET, ZDT_FLAG_NORMALIZE, ZdtError, ZdtParams,
-                   autotune, dt_aggregate, get_plan, load, params, plan_candidates, profile_collect, profile_enable,
+from ._lib import (ZDT_BF16, ZDT_F16, ZDT_F32, ZDT_FLAG_GUIDE_TARGET, ZDT_FLAG_NORMALIZE, ZDT_I8, ZDT_I16, ZdtError,
+                   ZdtParams, autotune, dt_aggregate, get_plan, i8_codec, load, params, plan_candidates,
+                   profile_collect, profile_enable,
                    set_plan, stereo_solve, stereo_solve_batch, volume_size, workspace_size, wta_disparity,
                    zncc_cost_volume, zncc_window_sums)
 
-__all__ = ["ZDT_F32", "ZDT_F16", "ZDT_BF16", "ZDT_FLAG_NORMALIZE", "ZDT_FLAG_GUIDE_TARGET", "ZdtError", "ZdtParams",
+__all__ = ["ZDT_F32", "ZDT_F16", "ZDT_BF16", "ZDT_I16", "ZDT_I8", "ZDT_FLAG_NORMALIZE", "ZDT_FLAG_GUIDE_TARGET",
+           "ZdtError", "ZdtParams", "i8_codec",
            "params", "load", "zncc_cost_volume", "dt_aggregate", "wta_disparity", "stereo_solve",
            "stereo_solve_batch", "plan_candidates", "get_plan", "set_plan", "autotune", "zncc_window_sums",
            "workspace_size", "volume_size", "profile_enable", "profile_collect", "torch_dtype", "Solver"]
@@ -24,7 +26,8 @@ __all__ = ["ZDT_F32", "ZDT_F16", "ZDT_BF16", "ZDT_FLAG_NORMALIZE", "ZDT_FLAG_GUI
 
 def torch_dtype(vol_dtype):
     import torch
-    return {ZDT_F32: torch.float32, ZDT_F16: torch.float16, ZDT_BF16: torch.bfloat16}[vol_dtype]
+    return {ZDT_F32: torch.float32, ZDT_F16: torch.float16, ZDT_BF16: torch.bfloat16, ZDT_I16: torch.int16,
+            ZDT_I8: torch.uint8}[vol_dtype]
 
 
 class Solver:

@@ -14,14 +14,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libzdt.so")
 
 ZDT_OK, ZDT_EINVAL, ZDT_ENOMEM, ZDT_EHIP, ZDT_EUNSUPPORTED = 0, -1, -2, -3, -4
-ZDT_F32, ZDT_F16, ZDT_BF16 = 0, 1, 2
+ZDT_F32, ZDT_F16, ZDT_BF16, ZDT_I16, ZDT_I8 = 0, 1, 2, 3, 4
 ZDT_FLAG_NORMALIZE = 1
 ZDT_FLAG_GUIDE_TARGET = 2
 
 EXPORTED = ("zdt_workspace_size", "zdt_volume_size", "zncc_cost_volume", "dt_aggregate", "wta_disparity",
             "stereo_solve", "stereo_solve_batch", "zdt_plan_candidates", "zdt_get_plan", "zdt_set_plan",
-            "zdt_autotune", "zncc_window_sums", "zdt_last_error", "zdt_profile_enable", "zdt_profile_collect",
-            "zdt_profile_entry")
+            "zdt_autotune", "zncc_window_sums", "zdt_i8_codec", "zdt_last_error", "zdt_profile_enable",
+            "zdt_profile_collect", "zdt_profile_entry")
 
 
 class ZdtParams(ctypes.Structure):
@@ -77,12 +77,13 @@ def load():
     lib.zdt_get_plan.argtypes = [PP, PL]
     lib.zdt_set_plan.argtypes = [PP, PL]
     lib.zdt_autotune.argtypes = [PP, ctypes.c_char_p, PL, P]
+    lib.zdt_i8_codec.argtypes = [P, P, P, ctypes.c_int64, P]
     lib.zdt_last_error.restype = ctypes.c_char_p
     lib.zdt_profile_enable.argtypes = [ctypes.c_int]
     lib.zdt_profile_entry.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     for f in ("zncc_cost_volume", "dt_aggregate", "wta_disparity", "stereo_solve", "stereo_solve_batch",
-              "zdt_plan_candidates", "zdt_get_plan", "zdt_set_plan", "zdt_autotune", "zncc_window_sums",
+              "zdt_plan_candidates", "zdt_get_plan", "zdt_set_plan", "zdt_autotune", "zncc_window_sums", "zdt_i8_codec",
               "zdt_profile_enable", "zdt_profile_collect", "zdt_profile_entry"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
@@ -177,6 +178,12 @@ def autotune(p, cache_path=None, stream=None):
     path = None if cache_path is None else os.fsencode(cache_path)
     _check("zdt_autotune", load().zdt_autotune(ctypes.byref(p), path, ctypes.byref(out), _stream(stream)))
     return out.astuple()
+
+
+def i8_codec(values, codes, decoded, stream=None):
+    """Device test entry of the 8-bit code: codes = encode(values), decoded = decode(codes)."""
+    _check("zdt_i8_codec", load().zdt_i8_codec(_ptr(values), _ptr(codes), _ptr(decoded), values.numel(),
+                                              _stream(stream)))
 
 
 def zncc_window_sums(p, left, right, s_l=None, s_ll=None, s_t=None, s_tt=None, s_rt=None, stream=None):

@@ -115,6 +115,63 @@ struct Elem<bf16> {
   }
 };
 
+// Integer cost volumes of Sec. IV-C: the (nearly zero-mean) cost scaled by T
+// and rounded to a 16-bit integer (i16v), or that integer's 8-bit code (i8c).
+struct i16v {
+  int16_t v;
+};
+struct i8c {
+  uint8_t c;
+};
+template <typename T>
+constexpr bool is_int_vol() {
+  return std::is_same<T, i16v>::value || std::is_same<T, i8c>::value;
+}
+
+// float -> int16 with round-to-nearest-even and saturation.
+__device__ __forceinline__ int sat16(float v) { return (int)fminf(fmaxf(rintf(v), -32768.0f), 32767.0f); }
+
+// 8-bit code of a 16-bit value (Sec. IV-C): non-negative values give 0; a
+// negative value keeps the six bits below its leading ones at bit 9, 5 or 1
+// (it lies below -2048, in [-2048, -128) or in [-128, 0)) with flag 1, 2 or 3.
+__device__ __forceinline__ uint32_t i8_encode(int v) {
+  const int pos = v < -2048 ? 9 : (v < -128 ? 5 : 1);
+  const uint32_t flag = v < -2048 ? 1u : (v < -128 ? 2u : 3u);
+  const uint32_t code = ((((uint32_t)v >> pos) & 0x3Fu) << 2) | flag;
+  return v < 0 ? code : 0u;
+}
+// Its inverse: the six bits back at their position, ones above, zeros below
+// (0, and the never-produced flag 0, give 0).
+__device__ __forceinline__ int i8_decode(uint32_t c) {
+  const uint32_t flag = c & 3u;
+  const int pos = flag == 1u ? 9 : (flag == 2u ? 5 : 1);
+  const int v = (int)((0xFFFFFFFFu << (pos + 6)) | ((c >> 2) << pos));  // sign-extended
+  return flag ? v : 0;
+}
+
+template <>
+struct Elem<i16v> {
+  static __device__ __forceinline__ float load(const i16v* p) { return (float)p->v; }
+  static __device__ __forceinline__ float bload(rsrc_t r, uint32_t voff, uint32_t soff) {
+    return (float)(short)__builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
+  }
+  static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t voff, uint32_t soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b16((unsigned short)sat16(v), r, (int)voff, (int)soff, 0);
+  }
+  static __device__ __forceinline__ void store(i16v* p, float v) { p->v = (int16_t)sat16(v); }
+};
+template <>
+struct Elem<i8c> {
+  static __device__ __forceinline__ float load(const i8c* p) { return (float)i8_decode(p->c); }
+  static __device__ __forceinline__ float bload(rsrc_t r, uint32_t voff, uint32_t soff) {
+    return (float)i8_decode(__builtin_amdgcn_raw_buffer_load_b8(r, (int)voff, (int)soff, 0));
+  }
+  static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t voff, uint32_t soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b8((unsigned char)i8_encode(sat16(v)), r, (int)voff, (int)soff, 0);
+  }
+  static __device__ __forceinline__ void store(i8c* p, float v) { p->c = (uint8_t)i8_encode(sat16(v)); }
+};
+
 __host__ __device__ constexpr int packs_of(int R) { return (2 * R + 1 + 3) / 4; }
 
 // Register discipline for the unrolled recursions.  Without it the compiler
@@ -229,6 +286,8 @@ struct HArgs {
   const uint8_t* guide;
   int pitch, W, H, D;
   float inv_sigma_s, range_coef, out_scale;
+  float in_scale;        // integer volumes: 1/T applied to every loaded value
+  const float* ref0;     // integer volumes: raw cost at d = 0 [H][W], subtracted before the first pass
   void* vol;
   int32_t* s_rt;
   int32_t* s_l;
@@ -252,6 +311,7 @@ struct HJob {
   void* vol;
   const float* g_in;
   float* g_out;
+  const float* ref0;
 };
 struct HJobs {
   HJob j[kMaxJobs];
@@ -535,13 +595,15 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
     a.vol = jb.vol;
     a.g_in = jb.g_in;
     a.g_out = jb.g_out;
+    a.ref0 = jb.ref0;
   }
   constexpr int NW = 2 * R + 1;  // window side
   constexpr int N = NW * NW;
   constexpr int SPW = kWave / LPS;  // segments per wave
   constexpr bool kZncc = MODE != kHPair;
   constexpr bool kDT = MODE == kCostHPair || MODE == kHPair;
-  constexpr bool kHalf = std::is_same<T, f16x>::value;  // exponent-scaled FP16
+  constexpr bool kHalf = std::is_same<T, f16x>::value;  // gain-scaled FP16
+  constexpr bool kInt = is_int_vol<T>();                 // T-scaled, centred integer volume
   static_assert(LPS == 64 || LPS == 32, "lanes per segment");
   constexpr uint32_t kBytes = sizeof(T);
   int y, chunk;
@@ -569,7 +631,7 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
   // array offsets are compile-time constants (one base register per index
   // pattern instead of one per array); streaming modes size it for this row.
   constexpr int kWMax = (kWave / LPS) * kMaxWaves * SEG;
-  const HLayout lay = h_layout(kDT ? kWMax : W, R, LPS, SEG, kZncc, kDT, kHalf);
+  const HLayout lay = h_layout(kDT ? kWMax : W, R, LPS, SEG, kZncc, kDT, kHalf || kInt);
   if constexpr (kZncc) stage_zncc<R, LPS>(a, lay, smem, y, d0, MODE);
   if constexpr (kDT) stage_row_weights(a, (float*)(smem + lay.oWH), y);
   float* GI = (float*)(smem + lay.oGI);
@@ -577,6 +639,10 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
   if constexpr (kHalf && MODE == kHPair) {
     const float* gr = a.g_in + (size_t)y * W;  // gains of the stored input row
     for (int x = threadIdx.x; x < W; x += blockDim.x) GI[x] = gr[x];
+  }
+  if constexpr (kInt && MODE == kCostHPair) {
+    const float* rr = a.ref0 + (size_t)y * W;  // the row's raw cost at d = 0
+    for (int x = threadIdx.x; x < W; x += blockDim.x) GI[x] = rr[x];
   }
   __syncthreads();
 
@@ -681,11 +747,13 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
         }
       }
       fence();
+      const float* r0 = GI + x0;  // integer volumes: the d = 0 cost, subtracted (Eq. DT_new with d_arb = 0)
 #pragma unroll
       for (int k = 0; k < SEG; ++k) {
         const bool in = k < len;
         const int x = x0 + k;
         c[k] = zncc_cost_from(__float_as_uint(c[k]), LS[x], LI[x], TS[x + LPS - 1 - dloc], TI[x + LPS - 1 - dloc], N);
+        if constexpr (kInt) c[k] -= r0[k];
         const float w = wp[k];
         ell = in ? fmaf(w, ell, c[k]) : ell;
         P = in ? P * w : P;
@@ -696,7 +764,10 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < SEG; ++k) c[k] = Elem<T>::bload(vrs, voff, step_soff(k));
+      for (int k = 0; k < SEG; ++k) {
+        c[k] = Elem<T>::bload(vrs, voff, step_soff(k));
+        if constexpr (kInt) c[k] *= a.in_scale;
+      }
       __builtin_amdgcn_sched_barrier(0);
       const float* gi = GI + x0;  // gains of the stored input at x0 + k
 #pragma unroll
@@ -763,6 +834,7 @@ struct VArgs {
   const uint8_t* guide;
   int pitch, W, H, D;
   float inv_sigma_s, range_coef, out_scale;
+  float in_scale;      // integer volumes: 1/T applied to every loaded value
   void* vol;
   const float* g_in;   // FP16 working volume: gain map [H][W] of the stored input
   float* g_out;        // and of the output (not for the WTA pass)
@@ -792,6 +864,13 @@ struct VJobs {
 __host__ __device__ inline int v_lds_words(int H, int SEG, bool scaled) {
   return (H + 1 + SEG) + 2 * (kMaxWaves * kWave + kMaxSegs) + (scaled ? 2 * (H + SEG) : 0);
 }
+
+// Order-preserving 32-bit key of a float (-0 folded onto +0) and its inverse.
+__device__ __forceinline__ uint32_t order_key(float v) {
+  const uint32_t u = __float_as_uint(v + 0.0f);
+  return (u >> 31) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float key_value(uint32_t k) { return __uint_as_float((k >> 31) ? (k & 0x7FFFFFFFu) : ~k); }
 
 // Wave (LANES = 64) or half-wave (LANES = 32) minimum of B independent keys at
 // once; the result is in lane 63 (and lane 31 for the lower half-wave).
@@ -833,7 +912,8 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs args, VJobs jobs) {
     a.part_val = jb.part_val;
     a.part_idx = jb.part_idx;
   }
-  constexpr bool kHalf = std::is_same<T, f16x>::value;  // exponent-scaled FP16
+  constexpr bool kHalf = std::is_same<T, f16x>::value;  // gain-scaled FP16
+  constexpr bool kInt = is_int_vol<T>();                 // T-scaled integer volume
   static_assert(LPS == 64 || (LPS == 32 && FULL), "two segments per wave need full segments");
   constexpr int SPW = kWave / LPS;
   constexpr uint32_t kBytes = sizeof(T);
@@ -896,7 +976,10 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs args, VJobs jobs) {
 
   float c[SEG];
 #pragma unroll
-  for (int k = 0; k < SEG; ++k) c[k] = Elem<T>::bload(vrs, voff, step_off(k));
+  for (int k = 0; k < SEG; ++k) {
+    c[k] = Elem<T>::bload(vrs, voff, step_off(k));
+    if constexpr (kInt) c[k] *= a.in_scale;
+  }
   __builtin_amdgcn_sched_barrier(0);
   // ---- loop A: carry-free U pass (decoding scaled FP16 values on the way)
   float ell = 0.0f, P = 1.0f;
@@ -965,11 +1048,17 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs args, VJobs jobs) {
   } else {
     // argmin over the chunk's disparities, lowest d on ties (Eq. WTA1).  The
     // aggregated costs are >= 0, so their bit patterns order like the values
-    // (|.| folds a -0 onto +0); idle lanes hold +inf.  Pixels are reduced 8 at
-    // a time with their DPP chains interleaved; pixel k of a segment keeps its
-    // (argmin, minimum) in lane k % LPS of that segment's lanes, in result
-    // register k / LPS, and the results leave in one store per register.
-    const uint32_t kInf = 0x7F800000u;
+    // (|.| folds a -0 onto +0); the centred integer volumes can be negative and
+    // use the sign-aware key instead.  Idle lanes hold +inf.  Pixels are
+    // reduced 8 at a time with their DPP chains interleaved; pixel k of a
+    // segment keeps its (argmin, minimum) in lane k % LPS of that segment's
+    // lanes, in result register k / LPS, and the results leave in one store
+    // per register.
+    auto key = [](float v) -> uint32_t {
+      if constexpr (kInt) return order_key(v);
+      return __float_as_uint(v) & 0x7FFFFFFFu;
+    };
+    const uint32_t kInf = key(__builtin_inff());
     constexpr int NR = (SEG + LPS - 1) / LPS;
     constexpr int B = 8;
     int rd[NR];
@@ -985,7 +1074,7 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs args, VJobs jobs) {
 #pragma unroll
       for (int i = 0; i < B; ++i) {
         const int k = min(k0 + i, SEG - 1);
-        v[i] = act ? (__float_as_uint(c[k]) & 0x7FFFFFFFu) : kInf;
+        v[i] = act ? key(c[k]) : kInf;
         m[i] = v[i];
       }
       group_min_u32<B, LPS>(m);
@@ -1021,7 +1110,7 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs args, VJobs jobs) {
         if (a.disp) {
           a.disp[p] = rd[r];
         } else {
-          a.part_val[(size_t)chunk * W * H + p] = __uint_as_float(rv[r]);
+          a.part_val[(size_t)chunk * W * H + p] = kInt ? key_value(rv[r]) : __uint_as_float(rv[r]);
           a.part_idx[(size_t)chunk * W * H + p] = rd[r];
         }
       }
@@ -1052,6 +1141,16 @@ struct WJobs {
     }
   }
   jb.disp[p] = idx;
+}
+
+// Test entry of the 8-bit code: codes[i] = encode(in[i]), decoded[i] = decode(codes[i]).
+[[maybe_unused]] static __global__ void i8_codec_kernel(const int16_t* in, uint8_t* codes, int16_t* decoded,
+                                                        int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t c = i8_encode(in[i]);
+  codes[i] = (uint8_t)c;
+  decoded[i] = (int16_t)i8_decode(c);
 }
 
 __device__ __forceinline__ float wave_min(float v) {

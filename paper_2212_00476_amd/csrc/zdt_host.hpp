@@ -66,6 +66,8 @@ ZDT_DECLARE_DISPATCH(f32)
 ZDT_DECLARE_DISPATCH(f16)
 ZDT_DECLARE_DISPATCH(bf16)
 ZDT_DECLARE_DISPATCH(f16x)
+ZDT_DECLARE_DISPATCH(i16)
+ZDT_DECLARE_DISPATCH(i8)
 #undef ZDT_DECLARE_DISPATCH
 
 }  // namespace zdt

@@ -12,7 +12,7 @@ template <int R, int SEG, int LPS, typename T, int MODE>
 int run_h(const HArgs& a, const HJobs& jobs, int n, hipStream_t s) {
   constexpr bool kDT = MODE == kCostHPair || MODE == kHPair;
   const int wl = kDT ? (kWave / LPS) * kMaxWaves * SEG : a.W;  // as in hpass_kernel
-  const HLayout lay = h_layout(wl, R, LPS, SEG, MODE != kHPair, kDT, std::is_same<T, f16x>::value);
+  const HLayout lay = h_layout(wl, R, LPS, SEG, MODE != kHPair, kDT, std::is_same<T, f16x>::value || is_int_vol<T>());
   static const char* const names[] = {"zncc_sums", "zncc_cost", "zncc_hpair", "dt_hpair"};
   const int spw = kWave / LPS;
   const int nw = (a.nseg + spw - 1) / spw;
@@ -115,7 +115,8 @@ int ZDT_CAT(dispatch_h_, ZDT_SUFFIX)(int mode, int R, int seg, int lps, const HA
   constexpr bool f16x_ = std::is_same<T, f16x>::value;
   switch (mode) {
     case kCost:
-      if constexpr (!f16x_) return inst::run_h_radius<T, kCost, 64>(R, seg, a, jobs, n, s);
+      if constexpr (!f16x_ && !std::is_same<T, i8c>::value)
+        return inst::run_h_radius<T, kCost, 64>(R, seg, a, jobs, n, s);
       break;
     case kCostHPair:
       if (lps == 32) return inst::run_h_radius<T, kCostHPair, 32>(R, seg, a, jobs, n, s);

@@ -103,7 +103,10 @@ namespace {
 // when formed in wrapping 32-bit arithmetic.
 constexpr int kMaxRadius = 7;
 
-size_t dtype_size(int t) { return t == ZDT_F32 ? 4 : 2; }
+size_t dtype_size(int t) { return t == ZDT_F32 ? 4 : (t == ZDT_I8 ? 1 : 2); }
+bool int_vol(int t) { return t == ZDT_I16 || t == ZDT_I8; }
+// The paper's integer coefficient T (Sec. IV-C, T = 21 in its system).
+constexpr float kIntScale = 21.0f;
 
 int check_params(const zdt_params* p, const char* who) {
   if (!p) return fail(ZDT_EINVAL, "%s: params is NULL", who);
@@ -117,7 +120,7 @@ int check_params(const zdt_params* p, const char* who) {
     return fail(ZDT_EINVAL, "%s: sigma_s must be finite and > 0", who);
   if (!(p->sigma_r > 0.0f)) return fail(ZDT_EINVAL, "%s: sigma_r must be > 0 (or +inf)", who);
   if (p->dt_iters < 0) return fail(ZDT_EINVAL, "%s: dt_iters must be >= 0", who);
-  if (p->vol_dtype < ZDT_F32 || p->vol_dtype > ZDT_BF16)
+  if (p->vol_dtype < ZDT_F32 || p->vol_dtype > ZDT_I8)
     return fail(ZDT_EINVAL, "%s: unknown vol_dtype %d", who, p->vol_dtype);
   if (p->flags & ~(ZDT_FLAG_NORMALIZE | ZDT_FLAG_GUIDE_TARGET))
     return fail(ZDT_EINVAL, "%s: unknown flags 0x%x", who, p->flags);
@@ -263,7 +266,9 @@ Plan plan_for(const zdt_params* p) {
   return it != g_plans.end() ? it->second : default_plan(p);
 }
 
-bool normalized(const zdt_params* p) { return (p->flags & ZDT_FLAG_NORMALIZE) || p->vol_dtype != ZDT_F32; }
+bool normalized(const zdt_params* p) {
+  return !int_vol(p->vol_dtype) && ((p->flags & ZDT_FLAG_NORMALIZE) || p->vol_dtype != ZDT_F32);
+}
 
 double one_minus_k(const zdt_params* p) { return -std::expm1(-1.0 / (double)p->sigma_s); }
 
@@ -291,6 +296,7 @@ HArgs make_hargs(const zdt_params* p, float out_scale) {
   a.inv_sigma_s = 1.0f / p->sigma_s;
   a.range_coef = range_coef(p);
   a.out_scale = out_scale;
+  a.in_scale = 1.0f;
   return a;
 }
 
@@ -303,6 +309,7 @@ VArgs make_vargs(const zdt_params* p, float out_scale) {
   a.inv_sigma_s = 1.0f / p->sigma_s;
   a.range_coef = range_coef(p);
   a.out_scale = out_scale;
+  a.in_scale = 1.0f;
   return a;
 }
 
@@ -327,6 +334,8 @@ int launch_h(const zdt_params* p, int dtype, int mode, bool scaled, HArgs a, con
     case ZDT_F16:
       return scaled ? dispatch_h_f16x(mode, R, sp.seg, lps, a, t, n, s) : dispatch_h_f16(mode, R, sp.seg, lps, a, t, n, s);
     case ZDT_BF16: return dispatch_h_bf16(mode, R, sp.seg, lps, a, t, n, s);
+    case ZDT_I16: return dispatch_h_i16(mode, R, sp.seg, lps, a, t, n, s);
+    case ZDT_I8: return dispatch_h_i8(mode, R, sp.seg, lps, a, t, n, s);
   }
   return fail(ZDT_EINVAL, "bad dtype %d", dtype);
 }
@@ -342,6 +351,8 @@ int launch_v(const zdt_params* p, bool scaled, bool wta, VArgs a, const VJobs& t
     case ZDT_F16:
       return scaled ? dispatch_v_f16x(sp.seg, lps, wta, a, t, n, s) : dispatch_v_f16(sp.seg, lps, wta, a, t, n, s);
     case ZDT_BF16: return dispatch_v_bf16(sp.seg, lps, wta, a, t, n, s);
+    case ZDT_I16: return dispatch_v_i16(sp.seg, lps, wta, a, t, n, s);
+    case ZDT_I8: return dispatch_v_i8(sp.seg, lps, wta, a, t, n, s);
   }
   return fail(ZDT_EINVAL, "bad dtype %d", p->vol_dtype);
 }
@@ -351,6 +362,8 @@ int dispatch_wta(int dtype, const void* vol, int npix, int D, int32_t* disp, hip
     case ZDT_F32: return dispatch_wta_f32(vol, npix, D, disp, s);
     case ZDT_F16: return dispatch_wta_f16(vol, npix, D, disp, s);
     case ZDT_BF16: return dispatch_wta_bf16(vol, npix, D, disp, s);
+    case ZDT_I16: return dispatch_wta_i16(vol, npix, D, disp, s);
+    case ZDT_I8: return dispatch_wta_i8(vol, npix, D, disp, s);
   }
   return fail(ZDT_EINVAL, "bad dtype %d", dtype);
 }
@@ -360,7 +373,7 @@ int dispatch_wta(int dtype, const void* vol, int npix, int D, int32_t* disp, hip
 // disparity chunks (one V lane per disparity; chunks of 32 or 64 disparities
 // depending on the plan, so the size covers 32).
 struct WsLayout {
-  size_t gain_a, gain_b, part_val, part_idx, total;
+  size_t gain_a, gain_b, ref0, part_val, part_idx, total;
 };
 size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 int wta_chunks(const zdt_params* p, int v_lanes) { return (p->max_disp + v_lanes - 1) / v_lanes; }
@@ -372,6 +385,10 @@ WsLayout ws_layout(const zdt_params* p) {
     L.gain_a = o;
     o += align256(npix * sizeof(float));
     L.gain_b = o;
+    o += align256(npix * sizeof(float));
+  }
+  if (int_vol(p->vol_dtype) && p->dt_iters > 0) {  // the raw cost at d = 0 (centring reference)
+    L.ref0 = o;
     o += align256(npix * sizeof(float));
   }
   if (p->dt_iters > 0 && wta_chunks(p, 32) > 1) {
@@ -399,7 +416,8 @@ int solve_group(const zdt_params* p, const JobPtrs* jobs, int n, hipStream_t s) 
   if (n < 1 || n > kMaxJobs) return fail(ZDT_EINVAL, "solve_group: %d jobs", n);
   const Plan pl = plan_for(p);
   const WsLayout L = ws_layout(p);
-  const bool scaled = p->vol_dtype == ZDT_F16;  // exponent-scaled FP16 working volume
+  const bool scaled = p->vol_dtype == ZDT_F16;  // gain-scaled FP16 working volume
+  const bool ints = int_vol(p->vol_dtype);       // T-scaled, centred integer volume
   const int vchunks = wta_chunks(p, pl.v_lanes);
   const bool multi = vchunks > 1;
   const size_t npix = (size_t)p->width * p->height;
@@ -413,18 +431,34 @@ int solve_group(const zdt_params* p, const JobPtrs* jobs, int n, hipStream_t s) 
     float* gb = scaled ? (float*)((char*)j.ws + L.gain_b) : nullptr;
     float* pv = multi ? (float*)((char*)j.ws + L.part_val) : nullptr;
     int32_t* pi = multi ? (int32_t*)((char*)j.ws + L.part_idx) : nullptr;
-    ht.j[i] = {j.left, j.right, guide, j.vol, gb, ga};                        // H pairs: B -> A
+    const float* r0 = ints ? (const float*)((char*)j.ws + L.ref0) : nullptr;
+    ht.j[i] = {j.left, j.right, guide, j.vol, gb, ga, r0};                    // H pairs: B -> A
     vt.j[i] = {guide, j.vol, ga, gb, multi ? nullptr : j.disp, pv, pi};      // V pairs: A -> B
     wt.j[i] = {pv, pi, j.disp};
   }
   // An FP16 working volume is scaled per pixel by its gain and needs no
-  // global scale; the other types take the (1-K)-per-pass normalisation.
-  const float sc = scaled ? 1.0f : pair_scale(p);
-  const HArgs ha = make_hargs(p, sc);
-  const VArgs va = make_vargs(p, sc);
+  // global scale; integer volumes store T times the value; the other types
+  // take the (1-K)-per-pass normalisation.
+  const float sc = scaled ? 1.0f : (ints ? kIntScale : pair_scale(p));
+  HArgs ha = make_hargs(p, sc);
+  VArgs va = make_vargs(p, sc);
+  ha.in_scale = va.in_scale = ints ? 1.0f / kIntScale : 1.0f;
+  int rc = ZDT_OK;
+  if (ints) {
+    // centring reference (Eq. DT_new with d_arb = 0): the raw cost slice d = 0,
+    // subtracted from every raw cost before the first pass.  The passes are
+    // linear and map the zero slice to zero, so every later stage stays centred.
+    zdt_params p0 = *p;
+    p0.max_disp = 1;
+    p0.vol_dtype = ZDT_F32;
+    HJobs rt{};
+    for (int i = 0; i < n; ++i)
+      rt.j[i] = {jobs[i].left, jobs[i].right, nullptr, (void*)ht.j[i].ref0, nullptr, nullptr, nullptr};
+    rc = launch_h(&p0, ZDT_F32, kCost, false, make_hargs(&p0, 1.0f), rt, n, pl, s);
+  }
   // sweep 1: cost fused with L, R; then U, D.  Sweeps 2..I: L, R; U, D.  The
   // last U, D pair carries the WTA and writes no volume.
-  int rc = launch_h(p, p->vol_dtype, kCostHPair, scaled, ha, ht, n, pl, s);
+  if (rc == ZDT_OK) rc = launch_h(p, p->vol_dtype, kCostHPair, scaled, ha, ht, n, pl, s);
   for (int it = 0; rc == ZDT_OK && it < p->dt_iters; ++it) {
     if (it > 0 && (rc = launch_h(p, p->vol_dtype, kHPair, scaled, ha, ht, n, pl, s))) break;
     rc = launch_v(p, scaled, it + 1 == p->dt_iters, va, vt, n, pl, s);
@@ -440,9 +474,10 @@ int solve_group(const zdt_params* p, const JobPtrs* jobs, int n, hipStream_t s) 
 // The raw-cost path (dt_iters = 0): streamed cost volume, then the WTA.
 int solve_raw(const zdt_params* p, const JobPtrs& j, hipStream_t s) {
   HJobs t{};
-  t.j[0] = {j.left, j.right, nullptr, j.vol, nullptr, nullptr};
+  t.j[0] = {j.left, j.right, nullptr, j.vol, nullptr, nullptr, nullptr};
   const Plan pl = plan_for(p);
-  int rc = launch_h(p, p->vol_dtype, kCost, false, make_hargs(p, 1.0f), t, 1, pl, s);
+  int rc = launch_h(p, p->vol_dtype, kCost, false, make_hargs(p, int_vol(p->vol_dtype) ? kIntScale : 1.0f), t, 1,
+                    pl, s);
   if (rc) return rc;
   return dispatch_wta(p->vol_dtype, j.vol, p->width * p->height, p->max_disp, j.disp, s);
 }
@@ -452,6 +487,8 @@ int check_job(const zdt_params* p, const uint8_t* left, const uint8_t* right, co
   int rc = check_params(p, who);
   if (rc) return rc;
   if (!left || !right || !disp || !vol) return fail(ZDT_EINVAL, "%s: NULL image, disparity or volume pointer", who);
+  if (p->vol_dtype == ZDT_I8 && p->dt_iters == 0)
+    return fail(ZDT_EUNSUPPORTED, "%s: 8-bit coded volumes need dt_iters >= 1 (raw costs code to zero)", who);
   if (p->dt_iters > 0) {
     const size_t need = ws_layout(p).total;
     if (need && !ws) return fail(ZDT_EINVAL, "%s: a workspace of %zu B is required", who, need);
@@ -503,8 +540,11 @@ int zncc_cost_volume(const zdt_params* p, const uint8_t* left, const uint8_t* ri
   if (rc) return rc;
   if (!left || !right || !cost) return fail(ZDT_EINVAL, "zncc_cost_volume: NULL image or volume pointer");
   HJobs t{};
-  t.j[0] = {left, right, nullptr, cost, nullptr, nullptr};
-  return launch_h(p, p->vol_dtype, kCost, false, make_hargs(p, 1.0f), t, 1, plan_for(p), (hipStream_t)stream);
+  if (p->vol_dtype == ZDT_I8)
+    return fail(ZDT_EUNSUPPORTED, "zncc_cost_volume: raw costs are non-negative, their 8-bit codes are all zero");
+  t.j[0] = {left, right, nullptr, cost, nullptr, nullptr, nullptr};
+  const float sc = int_vol(p->vol_dtype) ? kIntScale : 1.0f;
+  return launch_h(p, p->vol_dtype, kCost, false, make_hargs(p, sc), t, 1, plan_for(p), (hipStream_t)stream);
 }
 
 int zncc_window_sums(const zdt_params* p, const uint8_t* left, const uint8_t* right, int32_t* s_l, int32_t* s_ll,
@@ -519,7 +559,7 @@ int zncc_window_sums(const zdt_params* p, const uint8_t* left, const uint8_t* ri
   a.s_t = s_t;
   a.s_tt = s_tt;
   HJobs t{};
-  t.j[0] = {left, right, nullptr, nullptr, nullptr, nullptr};
+  t.j[0] = {left, right, nullptr, nullptr, nullptr, nullptr, nullptr};
   return launch_h(p, ZDT_F32, kSums, false, a, t, 1, plan_for(p), (hipStream_t)stream);
 }
 
@@ -527,11 +567,13 @@ int dt_aggregate(const zdt_params* p, const uint8_t* guide, void* cost, double* 
   int rc = check_params(p, "dt_aggregate");
   if (rc) return rc;
   if (!guide || !cost) return fail(ZDT_EINVAL, "dt_aggregate: NULL guide or volume pointer");
+  if (int_vol(p->vol_dtype))
+    return fail(ZDT_EUNSUPPORTED, "dt_aggregate: integer volumes are produced only inside stereo_solve");
   hipStream_t s = (hipStream_t)stream;
   const float sc = pair_scale(p);
   const Plan pl = plan_for(p);
   HJobs ht{};
-  ht.j[0] = {nullptr, nullptr, guide, cost, nullptr, nullptr};
+  ht.j[0] = {nullptr, nullptr, guide, cost, nullptr, nullptr, nullptr};
   VJobs vt{};
   vt.j[0] = {guide, cost, nullptr, nullptr, nullptr, nullptr, nullptr};
   for (int it = 0; it < p->dt_iters; ++it) {
@@ -712,6 +754,15 @@ int zdt_autotune(const zdt_params* p, const char* cache_path, zdt_plan* chosen, 
     std::fclose(f);
   }
   return ZDT_OK;
+}
+
+int zdt_i8_codec(const int16_t* values, uint8_t* codes, int16_t* decoded, int64_t n, void* stream) {
+  if (n < 0 || (n > 0 && (!values || !codes || !decoded)))
+    return fail(ZDT_EINVAL, "zdt_i8_codec: bad arguments (n = %lld)", (long long)n);
+  if (n == 0) return ZDT_OK;
+  const int threads = 256;
+  return launch("i8_codec", i8_codec_kernel, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads), 0,
+                (hipStream_t)stream, values, codes, decoded, n);
 }
 
 int zdt_profile_enable(int on) {

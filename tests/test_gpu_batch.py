@@ -61,7 +61,8 @@ class Job:
 MIX = [(320, 96, 32, 4, zdt.ZDT_F32, 3), (320, 96, 32, 4, zdt.ZDT_F32, 3), (320, 96, 32, 4, zdt.ZDT_F16, 3),
        (100, 17, 65, 3, zdt.ZDT_F32, 3), (320, 96, 32, 4, zdt.ZDT_F32, 3), (37, 23, 11, 2, zdt.ZDT_BF16, 3),
        (129, 33, 130, 0, zdt.ZDT_F32, 1), (100, 17, 65, 3, zdt.ZDT_F32, 3), (50, 40, 1, 1, zdt.ZDT_F32, 0),
-       (320, 96, 32, 4, zdt.ZDT_F16, 3), (200, 150, 200, 2, zdt.ZDT_F16, 2)]
+       (320, 96, 32, 4, zdt.ZDT_F16, 3), (200, 150, 200, 2, zdt.ZDT_F16, 2), (320, 96, 32, 1, zdt.ZDT_I16, 1),
+       (320, 96, 32, 1, zdt.ZDT_I8, 1), (320, 96, 32, 1, zdt.ZDT_I16, 1)]
 
 
 def test_batch_equals_separate_calls_mixed():

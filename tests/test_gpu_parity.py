@@ -463,3 +463,56 @@ def test_cost_bright_15x15_window_wraps_exactly():
     err = np.abs(host(cost).astype(np.float64) - want).max()
     note(f"  l=15 bright: max |d cost| = {err:.2e}")
     assert err <= 1e-5
+
+
+# ------------------------------------------------ integer volumes (Sec. IV-C)
+def test_i8_codec_on_device_matches_oracle():
+    """The device's 8-bit code, over every int16 value, bit for bit."""
+    v = torch.arange(-32768, 32768, dtype=torch.int32).to(torch.int16).cuda()
+    codes = torch.empty(v.shape, dtype=torch.uint8, device="cuda")
+    dec = torch.empty(v.shape, dtype=torch.int16, device="cuda")
+    zdt.i8_codec(v, codes, dec)
+    torch.cuda.synchronize()
+    want_codes = oracle.i8_encode(v.cpu().numpy())
+    assert np.array_equal(codes.cpu().numpy(), want_codes)
+    assert np.array_equal(dec.cpu().numpy(), oracle.i8_decode(want_codes))
+
+
+@pytest.mark.parametrize("dtype", [zdt.ZDT_I16, zdt.ZDT_I8], ids=["i16", "i8"])
+def test_integer_volume_centred_slice_is_zero(dtype):
+    """The d_arb = 0 slice is subtracted before the first pass; the passes map
+    a zero slice to zero, so every stored state has an all-zero slice d = 0."""
+    W, H, D, r = 160, 60, 40, 2
+    pr = pair_for(W, H, D, seed=13)
+    p = zdt.params(W, H, D, r, 5.0, 52.0 / 255.0, 2, vol_dtype=dtype)
+    s = zdt.Solver(p)
+    disp = s(dev(pr.left), dev(pr.right))
+    torch.cuda.synchronize()
+    vol = s.vol.cpu().numpy()           # holds the second H pair's output
+    assert np.all(vol[:, :, 0] == 0)
+    assert np.any(vol[:, :, 1:] != 0)
+    d = disp.cpu().numpy()
+    assert d.min() >= 0 and d.max() < D
+
+
+@pytest.mark.parametrize("dtype", [zdt.ZDT_I16, zdt.ZDT_I8], ids=["i16", "i8"])
+def test_integer_volumes_paper_configuration(dtype):
+    """1280x384, D = 128 at the paper's parameters with its narrow integer
+    volumes (T = 21, d_arb = 0; Int8 = 6-bit code + 2-bit flag).  These are
+    approximations whose accuracy the paper reports rather than bounds: the
+    disagreement with the FP64 oracle is reported; the assertion only catches
+    gross breakage (parity unpinned beyond the codec, which is bit-exact)."""
+    W, H, D = 1280, 384, 128
+    pr = scenes.workload("planes_1280x384_d128")
+    if "paper" not in _FULL:
+        c = oracle.solve_slices(pr.left, pr.right, PAPER["r"], range(D), PAPER["sigma_s"], PAPER["sigma_r"],
+                                PAPER["iters"], threads=ORACLE_THREADS)
+        _FULL["paper"] = np.ascontiguousarray(np.moveaxis(c, 0, 2))
+    o_disp = np.argmin(_FULL["paper"], axis=2)
+    p = zdt.params(W, H, D, PAPER["r"], PAPER["sigma_s"], PAPER["sigma_r"], PAPER["iters"], vol_dtype=dtype)
+    disp = zdt.Solver(p)(dev(pr.left), dev(pr.right)).cpu().numpy()
+    mism = (disp != o_disp).mean()
+    valid = pr.valid
+    mism_valid = (disp[valid] != o_disp[valid]).mean()
+    note(f"  paper configuration dtype={dtype}: mismatch {100 * mism:.3f} % (valid region {100 * mism_valid:.3f} %)")
+    assert mism <= 0.25

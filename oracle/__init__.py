@@ -57,6 +57,8 @@ def _load():
         lib.oracle_dt_aggregate.argtypes = [P, I, I, I, P, P, I]
         lib.oracle_wta.argtypes = [P, I, I, I, P]
         lib.oracle_stereo_solve.argtypes = [P, P, I, I, I, I, I, Dbl, Dbl, I, I, P, P]
+        lib.oracle_sgm_aggregate.argtypes = [P, I, I, I, Dbl, Dbl, Dbl, P]
+        lib.oracle_sgm_aggregate.restype = ctypes.c_int
         lib.oracle_i8_encode.argtypes = [ctypes.c_int16]
         lib.oracle_i8_encode.restype = ctypes.c_uint8
         lib.oracle_i8_decode.argtypes = [ctypes.c_uint8]
@@ -227,3 +229,13 @@ def i8_decode(codes):
     lib = _load()
     c = np.asarray(codes, np.uint8)
     return np.array([lib.oracle_i8_decode(int(x)) for x in c.ravel()], np.int16).reshape(c.shape)
+
+
+def sgm_aggregate(cost_hwd, p1, p2, scale):
+    """Four-path semi-global matching sum [H][W][D] (float64) of scale * cost."""
+    c = np.ascontiguousarray(cost_hwd, np.float64)
+    H, W, D = c.shape
+    out = np.empty_like(c)
+    _check(_load().oracle_sgm_aggregate(_ptr(c), W, H, D, float(p1), float(p2), float(scale), _ptr(out)),
+           "sgm_aggregate")
+    return out

@@ -297,3 +297,75 @@ int16_t oracle_i8_decode(uint8_t c) {
   const unsigned above = (0xFFFFu << (pos + 6)) & 0xFFFFu;
   return (int16_t)(uint16_t)(above | (six << pos));
 }
+
+/* ---------------------------------------------------------------------------
+ * Semi-global matching over four paths (the paper's system S1 combines its
+ * ZNCC with SGM, P1 = 18 and P2 = 185 on costs multiplied by T, Sec. V-D).
+ * Along a path r through pixels p_0, p_1, ...:
+ *   L(p_0, d) = C(p_0, d)
+ *   L(p_i, d) = C(p_i, d) + min( L(p_{i-1}, d),
+ *                                L(p_{i-1}, d - 1) + P1, L(p_{i-1}, d + 1) + P1,
+ *                                min_k L(p_{i-1}, k) + P2 ) - min_k L(p_{i-1}, k)
+ * (terms with d - 1 < 0 or d + 1 >= D left out).  Paths: left to right,
+ * right to left, top to bottom, bottom to top.  sum_hwd = the sum of the four
+ * L, with C = scale * cost.  cost_hwd and sum_hwd are [H][W][D].
+ */
+static void sgm_path(const double* cost, double* sum, int W, int D, double p1, double p2, double scale,
+                     const ptrdiff_t* pix, int n, double* prev, double* cur) {
+  for (int i = 0; i < n; ++i) {
+    const double* c = cost + pix[i] * D;
+    double m = 0.0;
+    if (i > 0) {
+      m = prev[0];
+      for (int k = 1; k < D; ++k) m = prev[k] < m ? prev[k] : m;
+    }
+    for (int d = 0; d < D; ++d) {
+      double v = scale * c[d];
+      if (i > 0) {
+        double best = prev[d];
+        if (d > 0 && prev[d - 1] + p1 < best) best = prev[d - 1] + p1;
+        if (d + 1 < D && prev[d + 1] + p1 < best) best = prev[d + 1] + p1;
+        if (m + p2 < best) best = m + p2;
+        v += best - m;
+      }
+      cur[d] = v;
+      sum[pix[i] * D + d] += v;
+    }
+    double* t = prev;
+    prev = cur;
+    cur = t;
+  }
+  (void)W;
+}
+
+int oracle_sgm_aggregate(const double* cost_hwd, int W, int H, int D, double p1, double p2, double scale,
+                         double* sum_hwd) {
+  if (W < 1 || H < 1 || D < 1 || !(p1 >= 0.0) || !(p2 >= p1)) return -1;
+  const int n = W > H ? W : H;
+  ptrdiff_t* pix = (ptrdiff_t*)malloc(sizeof(ptrdiff_t) * (size_t)n);
+  double* a = (double*)malloc(sizeof(double) * (size_t)D);
+  double* b = (double*)malloc(sizeof(double) * (size_t)D);
+  if (!pix || !a || !b) {
+    free(pix);
+    free(a);
+    free(b);
+    return -2;
+  }
+  memset(sum_hwd, 0, sizeof(double) * (size_t)W * H * D);
+  for (int y = 0; y < H; ++y) {
+    for (int x = 0; x < W; ++x) pix[x] = (ptrdiff_t)y * W + x;  /* left to right */
+    sgm_path(cost_hwd, sum_hwd, W, D, p1, p2, scale, pix, W, a, b);
+    for (int x = 0; x < W; ++x) pix[x] = (ptrdiff_t)y * W + (W - 1 - x);  /* right to left */
+    sgm_path(cost_hwd, sum_hwd, W, D, p1, p2, scale, pix, W, a, b);
+  }
+  for (int x = 0; x < W; ++x) {
+    for (int y = 0; y < H; ++y) pix[y] = (ptrdiff_t)y * W + x;  /* top to bottom */
+    sgm_path(cost_hwd, sum_hwd, W, D, p1, p2, scale, pix, H, a, b);
+    for (int y = 0; y < H; ++y) pix[y] = (ptrdiff_t)(H - 1 - y) * W + x;  /* bottom to top */
+    sgm_path(cost_hwd, sum_hwd, W, D, p1, p2, scale, pix, H, a, b);
+  }
+  free(pix);
+  free(a);
+  free(b);
+  return 0;
+}

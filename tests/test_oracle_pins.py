@@ -308,3 +308,45 @@ def test_i8_codec_round_trip_and_special_values():
     assert int(oracle.i8_decode(np.uint8(0))) == 0
     # codes with flag 00 are never produced
     assert not np.any((produced != 0) & ((produced & 3) == 0))
+
+
+# ------------------------------------------------ SGM, four paths (system S1)
+def _sgm_brute(c, p1, p2, scale):
+    """Each path as a dynamic program with an explicit penalty matrix over all
+    pairs (d, d'): 0 on the diagonal, P1 next to it, P2 elsewhere."""
+    H, W, D = c.shape
+    dd = np.abs(np.arange(D)[:, None] - np.arange(D)[None, :])
+    pen = np.where(dd == 0, 0.0, np.where(dd == 1, p1, p2))
+    out = np.zeros_like(c)
+
+    def run(seq):
+        prev = None
+        for (y, x) in seq:
+            cur = scale * c[y, x].copy()
+            if prev is not None:
+                cur += (prev[None, :] + pen).min(axis=1) - prev.min()
+            out[y, x] += cur
+            prev = cur
+    for y in range(H):
+        run([(y, x) for x in range(W)])
+        run([(y, x) for x in reversed(range(W))])
+    for x in range(W):
+        run([(y, x) for y in range(H)])
+        run([(y, x) for y in reversed(range(H))])
+    return out
+
+
+def test_sgm_against_explicit_penalty_dp():
+    rng = np.random.default_rng(17)
+    for shape, p1, p2 in (((5, 7, 6), 18.0, 185.0), ((4, 3, 9), 0.3, 1.1), ((1, 9, 4), 2.0, 2.0)):
+        c = rng.uniform(0.0, 2.0, shape)
+        got = oracle.sgm_aggregate(c, p1, p2, 21.0)
+        assert np.allclose(got, _sgm_brute(c, p1, p2, 21.0), rtol=0, atol=1e-9)
+
+
+def test_sgm_without_penalties_is_four_times_the_cost():
+    rng = np.random.default_rng(18)
+    c = rng.uniform(0.0, 2.0, (6, 8, 5))
+    assert np.array_equal(oracle.sgm_aggregate(c, 0.0, 0.0, 3.0), 4.0 * (3.0 * c))
+    one = rng.uniform(0.0, 2.0, (1, 1, 7))
+    assert np.array_equal(oracle.sgm_aggregate(one, 18.0, 185.0, 21.0), 4.0 * (21.0 * one))

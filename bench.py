@@ -8,7 +8,8 @@ same line carries the FP16 and BF16 forms, the unfused FP32 per-pair form, the
 roofline of the dominant kernel, the CPU oracle timed on a bounded sample, a
 48-pair mixed-shape batch (FP16, autotuned plans) and the continuous-batching
 server under Poisson arrivals (p50 / p99 latency, with every served result
-checked against the same pair solved alone).
+checked against the same pair solved alone), and the paper's system S1 (ZNCC
+costs into four-path SGM, then WTA) as one more form.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -50,6 +51,9 @@ def algorithmic_bytes(kernel, s):
         "dt_vpair": 2 * nvol * s + npix,
         "dt_vpair_wta": nvol * s + npix + 4 * npix,    # read the volume and guide; write disparities
         "wta": nvol * s + 4 * npix,
+        "sgm_rows": 2 * nvol * 4,                      # read the cost volume; write the sums
+        "sgm_cols": 3 * nvol * 4,                      # read costs and row sums; write the sums
+        "sgm_cols_wta": 2 * nvol * 4 + 4 * npix,       # read costs and row sums; write disparities
     }.get(kernel)
 
 
@@ -246,19 +250,30 @@ def main():
     forms["unfused_f32"] = {"ms_per_step": round(ms_u, 5), "gcost_evals_per_s": round(nvol / (ms_u * 1e-3) / 1e9, 3),
                             "fps": round(1000.0 / ms_u, 1)}
 
+    # the paper's system S1: ZNCC costs scaled by T = 21 into four-path SGM with
+    # P1 = 18, P2 = 185, then WTA (Sec. V-D)
+    p_s1 = zdt.params(W, H, D, R)
+    cost_s1 = torch.empty((H, W, D), dtype=torch.float32, device=dev)
+    sum_s1 = torch.empty_like(cost_s1)
+    disp_s1 = torch.empty((H, W), dtype=torch.int32, device=dev)
+
+    def s1():
+        zdt.stereo_solve_sgm(p_s1, L, Rt, disp_s1, cost_s1, sum_s1, 18.0, 185.0, 21.0)
+    ms_s1 = time_steps(s1, max(10, args.steps // 4), 5, torch)
+    forms["sgm_s1_f32"] = {"ms_per_step": round(ms_s1, 5), "gcost_evals_per_s": round(nvol / (ms_s1 * 1e-3) / 1e9, 3),
+                           "fps": round(1000.0 / ms_s1, 1), "p1": 18.0, "p2": 185.0, "cost_scale": 21.0}
+
     # per-kernel HIP-event times (recorded on the launch stream) over timed steps
-    def kernel_times(name):
-        solver, disp = solvers[name]
+    def kernel_times(fn, s):
         for _ in range(args.warmup):
-            solver(L, Rt, disp)
+            fn()
         torch.cuda.synchronize()
         zdt.profile_enable(True)
         for _ in range(args.steps):
-            solver(L, Rt, disp)
+            fn()
         torch.cuda.synchronize()
         kt = zdt.profile_collect()
         zdt.profile_enable(False)
-        s = 4 if name == "f32" else 2
         ks = {k: {"avg_us": round(1e3 * ms / n, 3), "launches": n} for k, (ms, n) in kt.items()}
         for k in ks:
             b = algorithmic_bytes(k, s)
@@ -266,9 +281,14 @@ def main():
                 ks[k]["GBps"] = round(b / (ks[k]["avg_us"] * 1e-6) / 1e9, 1)
         return kt, ks
 
-    kt, kernels = kernel_times("f32")
-    kernels_f16 = kernel_times("f16")[1]
-    kernels_bf16 = kernel_times("bf16")[1]
+    def solve_fn(name):
+        solver, disp = solvers[name]
+        return lambda: solver(L, Rt, disp)
+
+    kt, kernels = kernel_times(solve_fn("f32"), 4)
+    kernels_f16 = kernel_times(solve_fn("f16"), 2)[1]
+    kernels_bf16 = kernel_times(solve_fn("bf16"), 2)[1]
+    kernels_sgm = kernel_times(s1, 4)[1]
     dom = max(kt, key=lambda k: kt[k][0])
     avg_s = kt[dom][0] / kt[dom][1] * 1e-3
     abytes = algorithmic_bytes(dom, 4)
@@ -295,7 +315,7 @@ def main():
                    "sigma_s": SIGMA_S, "sigma_r": SIGMA_R, "dt_iters": ITERS, "vol_dtype": "f32",
                    "parallelism": "single-gpu"},
         "fps": f32["fps"], "forms": forms, "kernels_f32": kernels, "kernels_f16": kernels_f16,
-        "kernels_bf16": kernels_bf16, "roofline": roofline, "cpu_baseline": cpu,
+        "kernels_bf16": kernels_bf16, "kernels_sgm_s1": kernels_sgm, "roofline": roofline, "cpu_baseline": cpu,
         "p99_ms_served": served["poisson"]["p99_ms"] if served else None,
         "batch": batch, "serving": served,
         "window_sweep_cost_ms": sweep,

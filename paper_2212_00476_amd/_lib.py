@@ -20,8 +20,8 @@ ZDT_FLAG_GUIDE_TARGET = 2
 
 EXPORTED = ("zdt_workspace_size", "zdt_volume_size", "zncc_cost_volume", "dt_aggregate", "wta_disparity",
             "stereo_solve", "stereo_solve_batch", "zdt_plan_candidates", "zdt_get_plan", "zdt_set_plan",
-            "zdt_autotune", "zncc_window_sums", "zdt_i8_codec", "zdt_last_error", "zdt_profile_enable",
-            "zdt_profile_collect", "zdt_profile_entry")
+            "zdt_autotune", "zncc_window_sums", "zdt_i8_codec", "sgm_aggregate", "sgm_disparity",
+            "stereo_solve_sgm", "zdt_last_error", "zdt_profile_enable", "zdt_profile_collect", "zdt_profile_entry")
 
 
 class ZdtParams(ctypes.Structure):
@@ -78,13 +78,18 @@ def load():
     lib.zdt_set_plan.argtypes = [PP, PL]
     lib.zdt_autotune.argtypes = [PP, ctypes.c_char_p, PL, P]
     lib.zdt_i8_codec.argtypes = [P, P, P, ctypes.c_int64, P]
+    F = ctypes.c_float
+    lib.sgm_aggregate.argtypes = [PP, P, P, F, F, F, P]
+    lib.sgm_disparity.argtypes = [PP, P, P, P, F, F, F, P]
+    lib.stereo_solve_sgm.argtypes = [PP, P, P, P, P, P, F, F, F, P]
     lib.zdt_last_error.restype = ctypes.c_char_p
     lib.zdt_profile_enable.argtypes = [ctypes.c_int]
     lib.zdt_profile_entry.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     for f in ("zncc_cost_volume", "dt_aggregate", "wta_disparity", "stereo_solve", "stereo_solve_batch",
               "zdt_plan_candidates", "zdt_get_plan", "zdt_set_plan", "zdt_autotune", "zncc_window_sums", "zdt_i8_codec",
-              "zdt_profile_enable", "zdt_profile_collect", "zdt_profile_entry"):
+              "sgm_aggregate", "sgm_disparity", "stereo_solve_sgm", "zdt_profile_enable", "zdt_profile_collect",
+              "zdt_profile_entry"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -208,3 +213,22 @@ def profile_collect():
         _check("zdt_profile_entry", lib.zdt_profile_entry(i, ctypes.byref(name), ctypes.byref(ms), ctypes.byref(cnt)))
         out[name.value.decode()] = (ms.value, cnt.value)
     return out
+
+
+def sgm_aggregate(p, cost, out_sum, p1, p2, cost_scale, stream=None):
+    """Four-path SGM of an FP32 [H][W][D] cost volume into out_sum (see include/zdt.h)."""
+    _check("sgm_aggregate", load().sgm_aggregate(ctypes.byref(p), _ptr(cost), _ptr(out_sum), float(p1), float(p2),
+                                                 float(cost_scale), _stream(stream)))
+
+
+def sgm_disparity(p, cost, out_sum, disp, p1, p2, cost_scale, stream=None):
+    """Four-path SGM of an FP32 cost volume and its WTA into disp (out_sum is working memory)."""
+    _check("sgm_disparity", load().sgm_disparity(ctypes.byref(p), _ptr(cost), _ptr(out_sum), _ptr(disp), float(p1),
+                                                 float(p2), float(cost_scale), _stream(stream)))
+
+
+def stereo_solve_sgm(p, left, right, disp, cost, out_sum, p1, p2, cost_scale, stream=None):
+    """ZNCC cost, four-path SGM and WTA for one pair (the paper's system S1)."""
+    _check("stereo_solve_sgm", load().stereo_solve_sgm(ctypes.byref(p), _ptr(left), _ptr(right), _ptr(disp),
+                                                       _ptr(cost), _ptr(out_sum), float(p1), float(p2),
+                                                       float(cost_scale), _stream(stream)))

@@ -70,4 +70,16 @@ ZDT_DECLARE_DISPATCH(i16)
 ZDT_DECLARE_DISPATCH(i8)
 #undef ZDT_DECLARE_DISPATCH
 
+// Semi-global matching over an FP32 cost volume [H][W][D] (zdt_sgm.hip).
+// `sum` receives the row paths (vert = false), then the column paths are added
+// in place (vert = true), or with wta their sums go straight into `disp`.
+struct SgmArgs {
+  const float* cost;
+  float* sum;
+  int32_t* disp;
+  int W, H, D;
+  float p1, p2, scale;
+};
+int dispatch_sgm(const SgmArgs& a, bool vert, bool wta, hipStream_t s);
+
 }  // namespace zdt

@@ -217,6 +217,28 @@ def planes_pair(W=1280, H=384, D=128, seed=1, n_planes=None, noise=2.0):
     return _render(layers, H, W, D, rng, gain, bias, noise, seed)
 
 
+def cost_volume(W, H, D, seed=0, structured=True):
+    """Seeded float32 cost volume [H][W][D] with values in [0, 2] (the range of
+    1 - ZNCC), for aggregation tests that start from a given volume.  Plain:
+    independent uniform values.  Structured: each pixel has a true disparity
+    from a piecewise-planar field, and its costs grow with the distance to it,
+    plus uniform noise -- a volume with the minima a matching cost has."""
+    rng = np.random.default_rng(seed)
+    if not structured:
+        return rng.uniform(0.0, 2.0, (H, W, D)).astype(np.float32)
+    y, x = np.mgrid[0:H, 0:W].astype(np.float64)
+    true = np.zeros((H, W))
+    for k in range(4):  # four planes, the later ones over vertical bands
+        a, b, c = rng.uniform(0, D - 1), rng.uniform(-0.05, 0.05), rng.uniform(-0.05, 0.05)
+        plane = np.clip(a + b * (x - W / 2) + c * (y - H / 2), 0, D - 1)
+        band = (x >= k * W / 4) if k else np.ones_like(x, bool)
+        true = np.where(band, plane, true)
+    d = np.arange(D, dtype=np.float64)
+    cost = np.minimum(2.0, 0.04 * np.abs(d[None, None, :] - true[:, :, None]))
+    cost += rng.uniform(0.0, 0.3, cost.shape)
+    return np.minimum(cost, 2.0).astype(np.float32)
+
+
 def workload(name, seed=None):
     """The named synthetic workloads used by the tests and the benchmark."""
     if name == "bands_320x96_d32":

@@ -77,3 +77,21 @@ def test_reserved_fields_must_be_zero():
     p = zdt.params(64, 32, 16)
     p.reserved[2] = 1
     assert zdt.volume_size(p) == 0
+
+
+def test_sgm_argument_validation_without_device():
+    lib = zdt.load()
+    p = zdt.params(64, 32, 16)
+    n = 64 * 32 * 16 * 4
+    cost, out = ctypes.c_void_p(0x10000000), ctypes.c_void_p(0x10000000 + n)   # never dereferenced
+    sgm = lib.sgm_aggregate
+    assert sgm(ctypes.byref(p), None, out, 18.0, 185.0, 21.0, None) == _lib.ZDT_EINVAL
+    assert sgm(ctypes.byref(p), cost, ctypes.c_void_p(0x10000000 + n - 4), 18.0, 185.0, 21.0, None) == _lib.ZDT_EINVAL
+    assert "overlap" in lib.zdt_last_error().decode()
+    for p1, p2, s in ((-1.0, 185.0, 21.0), (18.0, 17.0, 21.0), (18.0, math.inf, 21.0), (math.nan, 185.0, 21.0),
+                      (18.0, 185.0, -1.0), (18.0, 185.0, math.inf)):
+        assert sgm(ctypes.byref(p), cost, out, p1, p2, s, None) == _lib.ZDT_EINVAL, (p1, p2, s)
+    for q in (zdt.params(64, 32, 16, vol_dtype=zdt.ZDT_F16), zdt.params(64, 32, 257)):
+        assert sgm(ctypes.byref(q), cost, out, 18.0, 185.0, 21.0, None) == _lib.ZDT_EUNSUPPORTED
+    assert lib.stereo_solve_sgm(ctypes.byref(p), None, None, None, cost, out, 18.0, 185.0, 21.0,
+                                None) == _lib.ZDT_EINVAL

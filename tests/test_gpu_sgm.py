@@ -1,0 +1,139 @@
+"""Parity of four-path semi-global matching (the aggregation of the paper's
+system S1, Sec. V-D) with the oracle, through the C ABI.
+
+Bar.  On each path the recursion is L_i = s C_i + G(L_{i-1}) - min L_{i-1},
+where G(L)(d) = min(L(d), L(d -+ 1) + P1, min L + P2) is monotone and commutes
+with adding a constant.  An error e in L_{i-1} therefore moves G(L) by an amount
+in [min e, max e] at every d, while the subtracted minimum moves by an amount
+in the same range.  So the spread of the error grows by at most twice the new
+rounding per pixel, and |e_i| <= spread(e_{i-1}) + rounding.  Every path value
+lies in [s C, s C + P2], so the four float32 roundings per element each stay
+within half an ulp of 2 Lmax, with Lmax = s max C + P2; that gives
+rounding <= 2 u, with u = ulp(2 Lmax).  An input error eps per cost adds
+s eps per step.  After n pixels, |e| <= 2 n (2 u + s eps); four paths and
+three additions then give the bound of `sgm_tol`.  A disparity may differ from
+the oracle's only where the oracle's own sums make it a near-tie within twice
+that bound.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2212_00476_amd import scenes
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+import paper_2212_00476_amd as zdt  # noqa: E402
+
+PAPER = (18.0, 185.0, 21.0)  # P1, P2 and the cost coefficient T of system S1
+
+
+def note(msg):
+    print(msg, flush=True)
+
+
+def sgm_tol(n, cost_max, p2, scale, eps=0.0):
+    lmax = scale * cost_max + p2
+    u = float(np.spacing(np.float32(2 * lmax)))
+    return 4 * 2 * n * (2 * u + scale * eps) + 2 * float(np.spacing(np.float32(4 * lmax)))
+
+
+def run_aggregate(cost, p1, p2, scale):
+    H, W, D = cost.shape
+    p = zdt.params(W, H, D)
+    c = torch.from_numpy(cost).cuda()
+    s = torch.full_like(c, float("nan"))
+    zdt.sgm_aggregate(p, c, s, p1, p2, scale)
+    disp = torch.full((H, W), -1, dtype=torch.int32, device="cuda")
+    s2 = torch.empty_like(c)
+    zdt.sgm_disparity(p, c, s2, disp, p1, p2, scale)
+    torch.cuda.synchronize()
+    return s.cpu().numpy(), disp.cpu().numpy()
+
+
+def check_near_ties(disp, ref_sum, tol):
+    H, W, D = ref_sum.shape
+    assert disp.min() >= 0 and disp.max() < D
+    got = np.take_along_axis(ref_sum, disp[..., None].astype(np.int64), axis=2)[..., 0]
+    gap = got - ref_sum.min(axis=2)
+    assert gap.max() <= 2 * tol, (gap.max(), tol)
+    return float((disp != ref_sum.argmin(axis=2)).mean())
+
+
+# (W, H, D): several lines and ragged halves, every values-per-lane count (D up
+# to 64, 128, 192, 256), padded lanes with vector loads (96, 200) and without
+# (150, 253), one pixel, one column, one row.
+SHAPES = [(37, 23, 16), (64, 40, 96), (45, 30, 128), (20, 17, 150), (33, 9, 200), (16, 12, 253), (1, 1, 5),
+          (1, 7, 64), (9, 1, 65), (70, 3, 256), (130, 66, 64), (24, 20, 129), (18, 22, 192)]
+PENALTIES = [PAPER, (0.5, 2.0, 1.0), (0.0, 0.0, 3.0)]
+
+
+@pytest.mark.parametrize("pen", PENALTIES, ids=["paper", "small", "none"])
+@pytest.mark.parametrize("shape", SHAPES, ids=["%dx%d_d%d" % s for s in SHAPES])
+def test_sgm_matches_oracle(shape, pen):
+    W, H, D = shape
+    p1, p2, scale = pen
+    seed = W * 1000 + H * 10 + D
+    cost = scenes.cost_volume(W, H, D, seed=seed, structured=seed % 2 == 0)
+    note("sgm %dx%d D=%d P1=%g P2=%g s=%g" % (W, H, D, p1, p2, scale))
+    got, disp = run_aggregate(cost, p1, p2, scale)
+    ref = oracle.sgm_aggregate(cost.astype(np.float64), p1, p2, scale)
+    tol = sgm_tol(max(W, H), float(cost.max()), p2, scale)
+    err = np.abs(got - ref)
+    assert np.all(np.isfinite(got))
+    assert err.max() <= tol, (err.max(), tol)
+    check_near_ties(disp, ref, tol)
+
+
+def test_sgm_full_size_1280x384_d128():
+    """The benchmark's launch configuration, checked on every element."""
+    W, H, D = 1280, 384, 128
+    cost = scenes.cost_volume(W, H, D, seed=7)
+    note("sgm full size %dx%d D=%d" % (W, H, D))
+    got, disp = run_aggregate(cost, *PAPER)
+    ref = oracle.sgm_aggregate(cost.astype(np.float64), *PAPER)
+    tol = sgm_tol(W, float(cost.max()), PAPER[1], PAPER[2])
+    err = np.abs(got - ref)
+    note("max |dS| = %.3g (bound %.3g), mean %.3g" % (err.max(), tol, err.mean()))
+    assert err.max() <= tol
+    mism = check_near_ties(disp, ref, tol)
+    note("disparities differing from the oracle's argmin: %.5f%%" % (100 * mism))
+    assert mism <= 1e-3
+
+
+@pytest.mark.parametrize("W,H,D,r", [(160, 64, 48, 2), (96, 40, 64, 1), (75, 33, 30, 4)])
+def test_stereo_solve_sgm_end_to_end(W, H, D, r):
+    """ZNCC cost, SGM and WTA on a synthetic pair against the FP64 oracle."""
+    pair = scenes.bands_pair(W=W, H=H, D=D, seed=W + r, band_disps=(2, D // 3, (2 * D) // 3))
+    p = zdt.params(W, H, D, radius=r)
+    note("stereo_solve_sgm %dx%d D=%d r=%d" % (W, H, D, r))
+    left, right = torch.from_numpy(pair.left).cuda(), torch.from_numpy(pair.right).cuda()
+    cost = torch.empty((H, W, D), dtype=torch.float32, device="cuda")
+    work = torch.empty_like(cost)
+    disp = torch.full((H, W), -1, dtype=torch.int32, device="cuda")
+    zdt.stereo_solve_sgm(p, left, right, disp, cost, work, *PAPER)
+    torch.cuda.synchronize()
+    ref_cost = oracle.zncc_cost(pair.left, pair.right, D, r)
+    ref = oracle.sgm_aggregate(ref_cost, *PAPER)
+    # the device cost is within 1e-5 of the oracle's (the raw-cost bar)
+    tol = sgm_tol(max(W, H), 2.0, PAPER[1], PAPER[2], eps=1e-5)
+    mism = check_near_ties(disp.cpu().numpy(), ref, tol)
+    note("mismatch %.4f%%" % (100 * mism))
+    assert mism <= 0.01
+
+
+def test_sgm_calls_are_independent():
+    """Back-to-back calls on reused buffers: the second, smaller one sees nothing
+    of the first."""
+    big = scenes.cost_volume(50, 30, 70, seed=3)
+    small = scenes.cost_volume(20, 11, 33, seed=4)
+    c = torch.from_numpy(big).cuda()
+    s = torch.empty_like(c)
+    disp = torch.empty((30, 50), dtype=torch.int32, device="cuda")
+    zdt.sgm_disparity(zdt.params(50, 30, 70), c, s, disp, *PAPER)
+    cs = torch.from_numpy(small).cuda()
+    ss = s.view(-1)[: small.size].view(small.shape)
+    zdt.sgm_aggregate(zdt.params(20, 11, 33), cs, ss, *PAPER)
+    torch.cuda.synchronize()
+    ref = oracle.sgm_aggregate(small.astype(np.float64), *PAPER)
+    assert np.abs(ss.cpu().numpy() - ref).max() <= sgm_tol(20, float(small.max()), PAPER[1], PAPER[2])

@@ -51,9 +51,9 @@ def algorithmic_bytes(kernel, s):
         "dt_vpair": 2 * nvol * s + npix,
         "dt_vpair_wta": nvol * s + npix + 4 * npix,    # read the volume and guide; write disparities
         "wta": nvol * s + 4 * npix,
-        "sgm_rows": 2 * nvol * 4,                      # read the cost volume; write the sums
-        "sgm_cols": 3 * nvol * 4,                      # read costs and row sums; write the sums
-        "sgm_cols_wta": 2 * nvol * 4 + 4 * npix,       # read costs and row sums; write disparities
+        "sgm_rows": nvol * s + nvol * 4,               # read the costs; write the FP32 sums
+        "sgm_cols": nvol * s + 2 * nvol * 4,           # read costs and row sums; write the sums
+        "sgm_cols_wta": nvol * s + nvol * 4 + 4 * npix,  # read costs and row sums; write disparities
     }.get(kernel)
 
 
@@ -251,17 +251,25 @@ def main():
                             "fps": round(1000.0 / ms_u, 1)}
 
     # the paper's system S1: ZNCC costs scaled by T = 21 into four-path SGM with
-    # P1 = 18, P2 = 185, then WTA (Sec. V-D)
-    p_s1 = zdt.params(W, H, D, R)
-    cost_s1 = torch.empty((H, W, D), dtype=torch.float32, device=dev)
-    sum_s1 = torch.empty_like(cost_s1)
-    disp_s1 = torch.empty((H, W), dtype=torch.int32, device=dev)
+    # P1 = 18, P2 = 185, then WTA (Sec. V-D); FP32 costs, and FP16 costs with
+    # their disparities compared with the FP32 form's
+    sum_s1 = torch.empty((H, W, D), dtype=torch.float32, device=dev)
+    s1_fns, s1_ref = {}, None
+    for name, dt, tdt in (("sgm_s1_f32", zdt.ZDT_F32, torch.float32), ("sgm_s1_f16", zdt.ZDT_F16, torch.float16)):
+        p_s1 = zdt.params(W, H, D, R, vol_dtype=dt)
+        cost_s1 = torch.empty((H, W, D), dtype=tdt, device=dev)
+        disp_s1 = torch.empty((H, W), dtype=torch.int32, device=dev)
 
-    def s1():
-        zdt.stereo_solve_sgm(p_s1, L, Rt, disp_s1, cost_s1, sum_s1, 18.0, 185.0, 21.0)
-    ms_s1 = time_steps(s1, max(10, args.steps // 4), 5, torch)
-    forms["sgm_s1_f32"] = {"ms_per_step": round(ms_s1, 5), "gcost_evals_per_s": round(nvol / (ms_s1 * 1e-3) / 1e9, 3),
-                           "fps": round(1000.0 / ms_s1, 1), "p1": 18.0, "p2": 185.0, "cost_scale": 21.0}
+        def s1(p_s1=p_s1, cost_s1=cost_s1, disp_s1=disp_s1):
+            zdt.stereo_solve_sgm(p_s1, L, Rt, disp_s1, cost_s1, sum_s1, 18.0, 185.0, 21.0)
+        s1_fns[name] = s1
+        ms_s1 = time_steps(s1, max(10, args.steps // 4), 5, torch)
+        forms[name] = {"ms_per_step": round(ms_s1, 5), "gcost_evals_per_s": round(nvol / (ms_s1 * 1e-3) / 1e9, 3),
+                       "fps": round(1000.0 / ms_s1, 1), "p1": 18.0, "p2": 185.0, "cost_scale": 21.0}
+        if s1_ref is None:
+            s1_ref = disp_s1
+        else:
+            forms[name]["disagreement_vs_f32"] = round(float((disp_s1 != s1_ref).float().mean()), 6)
 
     # per-kernel HIP-event times (recorded on the launch stream) over timed steps
     def kernel_times(fn, s):
@@ -288,7 +296,8 @@ def main():
     kt, kernels = kernel_times(solve_fn("f32"), 4)
     kernels_f16 = kernel_times(solve_fn("f16"), 2)[1]
     kernels_bf16 = kernel_times(solve_fn("bf16"), 2)[1]
-    kernels_sgm = kernel_times(s1, 4)[1]
+    kernels_sgm = kernel_times(s1_fns["sgm_s1_f32"], 4)[1]
+    kernels_sgm_f16 = kernel_times(s1_fns["sgm_s1_f16"], 2)[1]
     dom = max(kt, key=lambda k: kt[k][0])
     avg_s = kt[dom][0] / kt[dom][1] * 1e-3
     abytes = algorithmic_bytes(dom, 4)
@@ -315,7 +324,8 @@ def main():
                    "sigma_s": SIGMA_S, "sigma_r": SIGMA_R, "dt_iters": ITERS, "vol_dtype": "f32",
                    "parallelism": "single-gpu"},
         "fps": f32["fps"], "forms": forms, "kernels_f32": kernels, "kernels_f16": kernels_f16,
-        "kernels_bf16": kernels_bf16, "kernels_sgm_s1": kernels_sgm, "roofline": roofline, "cpu_baseline": cpu,
+        "kernels_bf16": kernels_bf16, "kernels_sgm_s1": kernels_sgm,
+        "kernels_sgm_s1_f16": kernels_sgm_f16, "roofline": roofline, "cpu_baseline": cpu,
         "p99_ms_served": served["poisson"]["p99_ms"] if served else None,
         "batch": batch, "serving": served,
         "window_sweep_cost_ms": sweep,

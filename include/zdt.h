@@ -147,13 +147,16 @@ int stereo_solve_batch(const zdt_job* jobs, int32_t n, void* stream);
  *   L(p,d) = s*C(p,d) + min(L(q,d), L(q,d-1) + P1, L(q,d+1) + P1, m(q) + P2) - m(q),
  *   m(q) = min_k L(q,k),   L(p,d) = s*C(p,d) on a path's first pixel,
  * and sum_hwd(p,d) = the sum of the four L(p,d).  s is `cost_scale`.
- *   cost_hwd  FP32 [H][W][D] DEVICE volume, read only (e.g. zncc_cost_volume)
+ *   cost_hwd  [H][W][D] DEVICE volume of params->vol_dtype, ZDT_F32 or ZDT_F16
+ *             (e.g. from zncc_cost_volume), read only; finite values
  *   sum_hwd   FP32 [H][W][D] DEVICE volume, written; must not overlap cost_hwd
- * params->vol_dtype must be ZDT_F32 and max_disp <= 256 (else
- * ZDT_EUNSUPPORTED); 0 <= p1 <= p2 < inf and a finite cost_scale >= 0 (else
- * ZDT_EINVAL).  The recursion runs in float32; rounding aside the result is
- * the four-path sum above.  wta_disparity() on sum_hwd completes the system. */
-int sgm_aggregate(const zdt_params* params, const float* cost_hwd, float* sum_hwd, float p1, float p2,
+ * Both volumes 16-byte aligned.  Other vol_dtypes or max_disp > 256 give
+ * ZDT_EUNSUPPORTED; penalties outside 0 <= p1 <= p2 < inf, a cost_scale that
+ * is negative or not finite, or NULL / misaligned / overlapping volumes give
+ * ZDT_EINVAL.  The recursion runs in float32 whatever the cost type; rounding
+ * aside the result is the four-path sum above.  wta_disparity() (with an F32
+ * vol_dtype) on sum_hwd completes the system. */
+int sgm_aggregate(const zdt_params* params, const void* cost_hwd, float* sum_hwd, float p1, float p2,
                   float cost_scale, void* stream);
 
 /* sgm_aggregate() followed by the WTA (Eq. WTA1: the smallest d of minimum
@@ -161,15 +164,15 @@ int sgm_aggregate(const zdt_params* params, const float* cost_hwd, float* sum_hw
  * are never stored: int32 disp_hw [H][W] (DEVICE).  sum_hwd is used as the
  * working volume; its contents on return are unspecified.  Same errors as
  * sgm_aggregate(), and ZDT_EINVAL for a NULL disp_hw. */
-int sgm_disparity(const zdt_params* params, const float* cost_hwd, float* sum_hwd, int32_t* disp_hw, float p1,
+int sgm_disparity(const zdt_params* params, const void* cost_hwd, float* sum_hwd, int32_t* disp_hw, float p1,
                   float p2, float cost_scale, void* stream);
 
 /* System S1 for one pair: zncc_cost_volume() into `cost_hwd`, then
- * sgm_disparity().  cost_hwd and sum_hwd are caller-owned FP32 volumes of
- * W*H*D floats each; their contents on return are unspecified.  Same errors as
- * sgm_disparity() and zncc_cost_volume(). */
+ * sgm_disparity().  cost_hwd (W*H*D elements of vol_dtype, F32 or F16) and
+ * sum_hwd (W*H*D floats) are caller-owned; their contents on return are
+ * unspecified.  Same errors as sgm_disparity() and zncc_cost_volume(). */
 int stereo_solve_sgm(const zdt_params* params, const uint8_t* left, const uint8_t* right, int32_t* disp_hw,
-                     float* cost_hwd, float* sum_hwd, float p1, float p2, float cost_scale, void* stream);
+                     void* cost_hwd, float* sum_hwd, float p1, float p2, float cost_scale, void* stream);
 
 /* Tile plan of the register-resident passes for one shape:
  *   h_lanes  lanes per horizontal segment: 32 (two segments per wave; the row

@@ -216,13 +216,13 @@ def profile_collect():
 
 
 def sgm_aggregate(p, cost, out_sum, p1, p2, cost_scale, stream=None):
-    """Four-path SGM of an FP32 [H][W][D] cost volume into out_sum (see include/zdt.h)."""
+    """Four-path SGM of an [H][W][D] cost volume (FP32 or FP16, p.vol_dtype) into the FP32 out_sum."""
     _check("sgm_aggregate", load().sgm_aggregate(ctypes.byref(p), _ptr(cost), _ptr(out_sum), float(p1), float(p2),
                                                  float(cost_scale), _stream(stream)))
 
 
 def sgm_disparity(p, cost, out_sum, disp, p1, p2, cost_scale, stream=None):
-    """Four-path SGM of an FP32 cost volume and its WTA into disp (out_sum is working memory)."""
+    """Four-path SGM of a cost volume (FP32 or FP16) and its WTA into disp (out_sum: FP32 working memory)."""
     _check("sgm_disparity", load().sgm_disparity(ctypes.byref(p), _ptr(cost), _ptr(out_sum), _ptr(disp), float(p1),
                                                  float(p2), float(cost_scale), _stream(stream)))
 

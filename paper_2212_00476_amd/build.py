@@ -25,6 +25,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Rpass-analysis=kernel-resource-usage"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-result",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC] + DEVICE_FLAGS
+# Per-source flags.  The SGM kernels take minima of values that are never NaN
+# for finite costs; without NaN semantics the compiler drops the quieting of
+# every operand (one extra VALU instruction per minimum on the serial path).
+SOURCE_FLAGS = {"zdt_sgm.hip": ["-fno-honor-nans"]}
 # Per-lane scratch above this fails the build: every kernel here keeps its
 # working set in registers and LDS, so more than a few spilled words means the
 # register allocation went wrong.  (One way it has gone wrong: the compiler
@@ -62,7 +66,7 @@ def build(verbose: bool = False) -> str:
 
     def compile_one(src):
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
-        cmd = [HIPCC] + COMMON + ["-c", src, "-o", obj]
+        cmd = [HIPCC] + COMMON + SOURCE_FLAGS.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         text = r.stdout + r.stderr
         msgs, held, in_remark = [], [], False

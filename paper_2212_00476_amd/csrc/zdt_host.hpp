@@ -70,11 +70,13 @@ ZDT_DECLARE_DISPATCH(i16)
 ZDT_DECLARE_DISPATCH(i8)
 #undef ZDT_DECLARE_DISPATCH
 
-// Semi-global matching over an FP32 cost volume [H][W][D] (zdt_sgm.hip).
-// `sum` receives the row paths (vert = false), then the column paths are added
-// in place (vert = true), or with wta their sums go straight into `disp`.
+// Semi-global matching over a cost volume [H][W][D], FP32 or (cost_f16) FP16
+// (zdt_sgm.hip).  The FP32 `sum` receives the row paths (vert = false), then
+// the column paths are added in place (vert = true), or with wta their sums go
+// straight into `disp`.
 struct SgmArgs {
-  const float* cost;
+  const void* cost;
+  int cost_f16;
   float* sum;
   int32_t* disp;
   int W, H, D;

@@ -635,30 +635,34 @@ int stereo_solve_batch(const zdt_job* jobs, int32_t n, void* stream) {
 }
 
 namespace {
-// Shared checks of the SGM entry points: FP32 volumes, D <= 256 (four
-// disparities per lane), 0 <= P1 <= P2 and a finite non-negative cost scale.
-int check_sgm(const zdt_params* p, const float* cost, const float* sum, float p1, float p2, float scale,
+// Shared checks of the SGM entry points: an FP32 or FP16 cost volume, an FP32
+// sum volume, both 16-byte aligned and disjoint, D <= 256 (four disparities per
+// lane), 0 <= P1 <= P2 and a finite non-negative cost scale.
+int check_sgm(const zdt_params* p, const void* cost, const float* sum, float p1, float p2, float scale,
               const char* who) {
   int rc = check_params(p, who);
   if (rc) return rc;
-  if (p->vol_dtype != ZDT_F32) return fail(ZDT_EUNSUPPORTED, "%s: SGM volumes are FP32 (vol_dtype 0)", who);
+  if (p->vol_dtype != ZDT_F32 && p->vol_dtype != ZDT_F16)
+    return fail(ZDT_EUNSUPPORTED, "%s: SGM cost volumes are FP32 or FP16 (vol_dtype 0 or 1)", who);
   if (p->max_disp > 4 * kWave) return fail(ZDT_EUNSUPPORTED, "%s: max_disp %d > %d", who, p->max_disp, 4 * kWave);
   if (!(p1 >= 0.0f) || !(p2 >= p1) || std::isinf(p2))
     return fail(ZDT_EINVAL, "%s: penalties need 0 <= P1 <= P2 < inf (got %g, %g)", who, p1, p2);
   if (!(scale >= 0.0f) || std::isinf(scale)) return fail(ZDT_EINVAL, "%s: cost scale must be finite, >= 0", who);
   if (!cost || !sum) return fail(ZDT_EINVAL, "%s: NULL cost or sum volume", who);
-  const size_t bytes = (size_t)p->width * p->height * p->max_disp * 4;
+  if (((uintptr_t)cost | (uintptr_t)sum) & 15) return fail(ZDT_EINVAL, "%s: volumes must be 16-byte aligned", who);
+  const size_t n = (size_t)p->width * p->height * p->max_disp;
   const char *c = (const char*)cost, *q = (const char*)sum;
-  if (c < q + bytes && q < c + bytes) return fail(ZDT_EINVAL, "%s: the cost and sum volumes overlap", who);
+  if (c < q + n * 4 && q < c + n * dtype_size(p->vol_dtype))
+    return fail(ZDT_EINVAL, "%s: the cost and sum volumes overlap", who);
   return ZDT_OK;
 }
 
-SgmArgs sgm_args(const zdt_params* p, const float* cost, float* sum, int32_t* disp, float p1, float p2, float scale) {
-  return SgmArgs{cost, sum, disp, p->width, p->height, p->max_disp, p1, p2, scale};
+SgmArgs sgm_args(const zdt_params* p, const void* cost, float* sum, int32_t* disp, float p1, float p2, float scale) {
+  return SgmArgs{cost, p->vol_dtype == ZDT_F16, sum, disp, p->width, p->height, p->max_disp, p1, p2, scale};
 }
 }  // namespace
 
-int sgm_aggregate(const zdt_params* p, const float* cost, float* sum, float p1, float p2, float cost_scale,
+int sgm_aggregate(const zdt_params* p, const void* cost, float* sum, float p1, float p2, float cost_scale,
                   void* stream) {
   int rc = check_sgm(p, cost, sum, p1, p2, cost_scale, "sgm_aggregate");
   if (rc) return rc;
@@ -668,7 +672,7 @@ int sgm_aggregate(const zdt_params* p, const float* cost, float* sum, float p1, 
   return dispatch_sgm(a, true, false, s);
 }
 
-int sgm_disparity(const zdt_params* p, const float* cost, float* sum, int32_t* disp, float p1, float p2,
+int sgm_disparity(const zdt_params* p, const void* cost, float* sum, int32_t* disp, float p1, float p2,
                   float cost_scale, void* stream) {
   int rc = check_sgm(p, cost, sum, p1, p2, cost_scale, "sgm_disparity");
   if (rc) return rc;
@@ -679,7 +683,7 @@ int sgm_disparity(const zdt_params* p, const float* cost, float* sum, int32_t* d
   return dispatch_sgm(a, true, true, s);
 }
 
-int stereo_solve_sgm(const zdt_params* p, const uint8_t* left, const uint8_t* right, int32_t* disp, float* cost,
+int stereo_solve_sgm(const zdt_params* p, const uint8_t* left, const uint8_t* right, int32_t* disp, void* cost,
                      float* sum, float p1, float p2, float cost_scale, void* stream) {
   int rc = check_sgm(p, cost, sum, p1, p2, cost_scale, "stereo_solve_sgm");
   if (rc) return rc;

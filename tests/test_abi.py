@@ -86,12 +86,18 @@ def test_sgm_argument_validation_without_device():
     cost, out = ctypes.c_void_p(0x10000000), ctypes.c_void_p(0x10000000 + n)   # never dereferenced
     sgm = lib.sgm_aggregate
     assert sgm(ctypes.byref(p), None, out, 18.0, 185.0, 21.0, None) == _lib.ZDT_EINVAL
-    assert sgm(ctypes.byref(p), cost, ctypes.c_void_p(0x10000000 + n - 4), 18.0, 185.0, 21.0, None) == _lib.ZDT_EINVAL
+    assert sgm(ctypes.byref(p), cost, ctypes.c_void_p(0x10000000 + n - 16), 18.0, 185.0, 21.0, None) == _lib.ZDT_EINVAL
     assert "overlap" in lib.zdt_last_error().decode()
     for p1, p2, s in ((-1.0, 185.0, 21.0), (18.0, 17.0, 21.0), (18.0, math.inf, 21.0), (math.nan, 185.0, 21.0),
                       (18.0, 185.0, -1.0), (18.0, 185.0, math.inf)):
         assert sgm(ctypes.byref(p), cost, out, p1, p2, s, None) == _lib.ZDT_EINVAL, (p1, p2, s)
-    for q in (zdt.params(64, 32, 16, vol_dtype=zdt.ZDT_F16), zdt.params(64, 32, 257)):
+    for q in (zdt.params(64, 32, 16, vol_dtype=zdt.ZDT_BF16), zdt.params(64, 32, 257)):
         assert sgm(ctypes.byref(q), cost, out, 18.0, 185.0, 21.0, None) == _lib.ZDT_EUNSUPPORTED
+    assert sgm(ctypes.byref(p), ctypes.c_void_p(0x10000008), out, 18.0, 185.0, 21.0, None) == _lib.ZDT_EINVAL
+    assert "aligned" in lib.zdt_last_error().decode()
+    # an FP16 cost volume is half the size: the FP32 sum may start right after it
+    h = zdt.params(64, 32, 16, vol_dtype=zdt.ZDT_F16)
+    assert sgm(ctypes.byref(h), cost, ctypes.c_void_p(0x10000000 + n // 2 - 16), 18.0, 185.0, 21.0,
+               None) == _lib.ZDT_EINVAL
     assert lib.stereo_solve_sgm(ctypes.byref(p), None, None, None, cost, out, 18.0, 185.0, 21.0,
                                 None) == _lib.ZDT_EINVAL

@@ -40,12 +40,12 @@ def sgm_tol(n, cost_max, p2, scale, eps=0.0):
 
 def run_aggregate(cost, p1, p2, scale):
     H, W, D = cost.shape
-    p = zdt.params(W, H, D)
+    p = zdt.params(W, H, D, vol_dtype=zdt.ZDT_F16 if cost.dtype == np.float16 else zdt.ZDT_F32)
     c = torch.from_numpy(cost).cuda()
-    s = torch.full_like(c, float("nan"))
+    s = torch.full(cost.shape, float("nan"), dtype=torch.float32, device="cuda")
     zdt.sgm_aggregate(p, c, s, p1, p2, scale)
     disp = torch.full((H, W), -1, dtype=torch.int32, device="cuda")
-    s2 = torch.empty_like(c)
+    s2 = torch.empty_like(s)
     zdt.sgm_disparity(p, c, s2, disp, p1, p2, scale)
     torch.cuda.synchronize()
     return s.cpu().numpy(), disp.cpu().numpy()
@@ -85,6 +85,23 @@ def test_sgm_matches_oracle(shape, pen):
     check_near_ties(disp, ref, tol)
 
 
+F16_SHAPES = [(37, 23, 16), (45, 30, 128), (20, 17, 150), (33, 9, 200), (1, 7, 64), (70, 3, 256)]
+
+
+@pytest.mark.parametrize("shape", F16_SHAPES, ids=["%dx%d_d%d" % s for s in F16_SHAPES])
+def test_sgm_fp16_costs_match_oracle(shape):
+    """FP16 cost volumes: the oracle takes the same FP16 values, so the bar is
+    unchanged (the recursion runs in float32 either way)."""
+    W, H, D = shape
+    cost = scenes.cost_volume(W, H, D, seed=W + H + D).astype(np.float16)
+    note("sgm fp16 costs %dx%d D=%d" % (W, H, D))
+    got, disp = run_aggregate(cost, *PAPER)
+    ref = oracle.sgm_aggregate(cost.astype(np.float64), *PAPER)
+    tol = sgm_tol(max(W, H), float(cost.max()), PAPER[1], PAPER[2])
+    assert np.abs(got - ref).max() <= tol
+    check_near_ties(disp, ref, tol)
+
+
 def test_sgm_full_size_1280x384_d128():
     """The benchmark's launch configuration, checked on every element."""
     W, H, D = 1280, 384, 128
@@ -101,22 +118,25 @@ def test_sgm_full_size_1280x384_d128():
     assert mism <= 1e-3
 
 
+@pytest.mark.parametrize("f16", [False, True], ids=["f32", "f16"])
 @pytest.mark.parametrize("W,H,D,r", [(160, 64, 48, 2), (96, 40, 64, 1), (75, 33, 30, 4)])
-def test_stereo_solve_sgm_end_to_end(W, H, D, r):
+def test_stereo_solve_sgm_end_to_end(W, H, D, r, f16):
     """ZNCC cost, SGM and WTA on a synthetic pair against the FP64 oracle."""
     pair = scenes.bands_pair(W=W, H=H, D=D, seed=W + r, band_disps=(2, D // 3, (2 * D) // 3))
-    p = zdt.params(W, H, D, radius=r)
-    note("stereo_solve_sgm %dx%d D=%d r=%d" % (W, H, D, r))
+    p = zdt.params(W, H, D, radius=r, vol_dtype=zdt.ZDT_F16 if f16 else zdt.ZDT_F32)
+    note("stereo_solve_sgm %dx%d D=%d r=%d %s" % (W, H, D, r, "f16" if f16 else "f32"))
     left, right = torch.from_numpy(pair.left).cuda(), torch.from_numpy(pair.right).cuda()
-    cost = torch.empty((H, W, D), dtype=torch.float32, device="cuda")
-    work = torch.empty_like(cost)
+    cost = torch.empty((H, W, D), dtype=torch.float16 if f16 else torch.float32, device="cuda")
+    work = torch.empty((H, W, D), dtype=torch.float32, device="cuda")
     disp = torch.full((H, W), -1, dtype=torch.int32, device="cuda")
     zdt.stereo_solve_sgm(p, left, right, disp, cost, work, *PAPER)
     torch.cuda.synchronize()
     ref_cost = oracle.zncc_cost(pair.left, pair.right, D, r)
     ref = oracle.sgm_aggregate(ref_cost, *PAPER)
-    # the device cost is within 1e-5 of the oracle's (the raw-cost bar)
-    tol = sgm_tol(max(W, H), 2.0, PAPER[1], PAPER[2], eps=1e-5)
+    # the device cost is within the raw-cost bar of the oracle's: 1e-5 in FP32,
+    # half an FP16 ulp of [1, 2) + 1e-6 in FP16
+    eps = 2.0 ** -11 + 1e-6 if f16 else 1e-5
+    tol = sgm_tol(max(W, H), 2.0, PAPER[1], PAPER[2], eps=eps)
     mism = check_near_ties(disp.cpu().numpy(), ref, tol)
     note("mismatch %.4f%%" % (100 * mism))
     assert mism <= 0.01

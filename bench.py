@@ -70,6 +70,15 @@ def measured_traffic(kernel, vol_dtype):
     return rec.get("bytes_per_launch")
 
 
+def d1_error_pct(disp, pr):
+    """KITTI 2015 style error rate on the synthetic ground truth: percent of the
+    valid pixels whose disparity is off by more than 3 px and more than 5 %."""
+    import numpy as np
+    err = np.abs(disp.cpu().numpy().astype(np.float64) - pr.gt)
+    bad = (err > 3.0) & (err > 0.05 * np.abs(pr.gt))
+    return round(100.0 * float(bad[pr.valid].mean()), 3)
+
+
 def time_steps(fn, steps, warmup, torch):
     for _ in range(warmup):
         fn()
@@ -201,7 +210,7 @@ def main():
         solvers[name] = (solver, disp)
         ms = time_steps(lambda: solver(L, Rt, disp), args.steps, args.warmup, torch)
         forms[name] = {"ms_per_step": round(ms, 5), "gcost_evals_per_s": round(nvol / (ms * 1e-3) / 1e9, 3),
-                       "fps": round(1000.0 / ms, 1)}
+                       "fps": round(1000.0 / ms, 1), "d1_error_pct": d1_error_pct(disp, pr)}
 
     # the paper's own system parameters: 3x3 window, one sweep, sigma_s = 5,
     # sigma_r = 52 on 0..255 (the configuration of its 32 fps Jetson TX2 figure)
@@ -216,7 +225,7 @@ def main():
         ms = time_steps(lambda: solver(L, Rt, disp), args.steps, args.warmup, torch)
         forms[name] = {"ms_per_step": round(ms, 5), "gcost_evals_per_s": round(nvol / (ms * 1e-3) / 1e9, 3),
                        "fps": round(1000.0 / ms, 1), "window": 3, "dt_iters": 1, "sigma_s": 5.0,
-                       "sigma_r": round(52.0 / 255.0, 6)}
+                       "sigma_r": round(52.0 / 255.0, 6), "d1_error_pct": d1_error_pct(disp, pr)}
         if paper_ref is None:
             paper_ref = disp.clone()
         else:
@@ -265,7 +274,8 @@ def main():
         s1_fns[name] = s1
         ms_s1 = time_steps(s1, max(10, args.steps // 4), 5, torch)
         forms[name] = {"ms_per_step": round(ms_s1, 5), "gcost_evals_per_s": round(nvol / (ms_s1 * 1e-3) / 1e9, 3),
-                       "fps": round(1000.0 / ms_s1, 1), "p1": 18.0, "p2": 185.0, "cost_scale": 21.0}
+                       "fps": round(1000.0 / ms_s1, 1), "p1": 18.0, "p2": 185.0, "cost_scale": 21.0,
+                       "d1_error_pct": d1_error_pct(disp_s1, pr)}
         if s1_ref is None:
             s1_ref = disp_s1
         else:

@@ -178,7 +178,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 48-pair batch")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs the whole pair on a single MI355X "
+        print("bench.py measures one GPU: the benchmark runs the whole pair on a single MI355X "
               "(sharding by disparity range is described, not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 

@@ -41,7 +41,7 @@ typedef enum zdt_status {
   ZDT_EINVAL = -1,          /* a parameter or pointer is invalid            */
   ZDT_ENOMEM = -2,          /* a host-side allocation failed                */
   ZDT_EHIP = -3,            /* a HIP call or kernel launch failed           */
-  ZDT_EUNSUPPORTED = -4     /* valid, but outside what this build supports  */
+  ZDT_EUNSUPPORTED = -4     /* valid, but outside what the library supports */
 } zdt_status;
 
 /* Volume element types.  ZDT_I16 and ZDT_I8 are the paper's narrow integer

@@ -99,11 +99,8 @@ struct Elem<f16x> {
 };
 template <>
 struct Elem<bf16> {
-  static __device__ __forceinline__ uint16_t encode(float v) {
-    uint32_t u = __float_as_uint(v);
-    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even (values are finite)
-    return (uint16_t)(u >> 16);
-  }
+  // round to nearest even: one v_cvt_pk_bf16_f32 on gfx950
+  static __device__ __forceinline__ uint16_t encode(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
   static __device__ __forceinline__ float load(const bf16* p) { return __uint_as_float((uint32_t)p->bits << 16); }
   static __device__ __forceinline__ void store(bf16* p, float v) { p->bits = encode(v); }
   static __device__ __forceinline__ float bload(rsrc_t r, uint32_t voff, uint32_t soff) {

@@ -68,7 +68,7 @@ def test_argument_validation_without_device():
     assert lib.zncc_cost_volume(ctypes.byref(good), None, None, None, None) == _lib.ZDT_EINVAL
     assert lib.dt_aggregate(ctypes.byref(good), None, None, None, None) == _lib.ZDT_EINVAL
     assert lib.wta_disparity(ctypes.byref(good), None, None, None) == _lib.ZDT_EINVAL
-    # outside this build's limits
+    # outside the library's limits
     for p in (zdt.params(64, 32, 16, radius=8), zdt.params(4000, 32, 16), zdt.params(64, 4000, 16)):
         assert lib.stereo_solve(ctypes.byref(p), None, None, None, None, None, None) == _lib.ZDT_EUNSUPPORTED
 

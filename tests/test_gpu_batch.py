@@ -6,7 +6,8 @@
   - every tile plan a shape admits agrees with the FP64 oracle to the usual
     end-to-end bar (FP32: mismatches only at near-ties of the oracle's own
     aggregated costs; FP16: <= 0.1 % of disparities);
-  - the largest batch shape, 1920x1080 with D = 256, agrees with the oracle
+  - the largest batch shape, 1920x1080 with D = 256, agrees with the oracle, and
+    so does the largest accepted extent, 1920x1152 with D = 480 (a 4.25 GB volume)
     over every pixel (oracle run slice by slice on the host);
   - the autotuner pins one of the candidates and caches it.
 """
@@ -180,6 +181,25 @@ def test_full_size_1920x1080_d256(dtype):
         assert ok.all(), slack[~ok].max()
     else:
         assert mism <= 1e-3
+
+
+def test_max_extent_1920x1152_d480():
+    """The largest shape the library accepts along every image axis at once:
+    the tallest column (16 segments of 72 rows), a 1920-wide row (32 segments
+    of 60), and D = 480, which puts the FP32 volume (4.25 GB) just under the
+    4 GiB limit of the 32-bit buffer offsets.  (The widest window, r = 7, is
+    covered at smaller sizes; here it would make the oracle take minutes.)"""
+    W, H, D, r = 1920, 1152, 480, 2
+    pr = scenes.planes_pair(W, H, D, seed=11)
+    p = zdt.params(W, H, D, r)
+    assert zdt.volume_size(p) == W * H * D * 4 < 1 << 32
+    note(f"{W}x{H} D={D} r={r}: GPU solve")
+    disp = zdt.Solver(p)(dev(pr.left), dev(pr.right)).cpu().numpy()
+    torch.cuda.empty_cache()
+    note(f"  oracle: {D} slices on {ORACLE_THREADS} threads, 32 at a time")
+    arg, slack, ok = _streamed_oracle_check(pr, D, r, disp)
+    note(f"  mismatch {100 * (disp != arg).mean():.4f} %")
+    assert ok.all(), slack[~ok].max()
 
 
 def test_autotune_pins_a_candidate_and_caches_it(tmp_path):

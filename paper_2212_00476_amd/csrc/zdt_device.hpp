@@ -889,6 +889,95 @@ __device__ __forceinline__ void group_min_u32(uint32_t (&m)[B]) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Butterfly minimum for the WTA of 64-lane segments.  A wave holds N pixels in
+// N registers (lane = disparity); reducing each over 64 lanes separately costs
+// six DPP steps per pixel.  Here the registers are merged pairwise instead,
+// six times: each merge takes the minimum over half of the remaining lanes of
+// two registers' pixels at once and keeps one pixel in each half of the lanes
+// (permlane32 / permlane16 swaps for the first two stages, then DPP row_ror:8,
+// row_half_mirror, quad_perm xor 2 and xor 1 with a lane select).  After six
+// stages every lane of the ceil-halved registers holds one pixel's minimum over
+// all 64 lanes; bfly_map() gives, at compile time, the register and lane of
+// each pixel.  An odd register is merged with itself.
+// ---------------------------------------------------------------------------
+constexpr int bfly_count(int n, int stages) { return stages == 0 ? n : bfly_count((n + 1) / 2, stages - 1); }
+
+template <int N>
+struct BflyMap {
+  int reg[N], lane[N];
+};
+
+// Label (pixel index) of every lane of every register through the six stages.
+template <int N>
+constexpr BflyMap<N> bfly_map() {
+  int lab[N][64] = {};
+  int nl[N][64] = {};
+  for (int r = 0; r < N; ++r)
+    for (int l = 0; l < 64; ++l) lab[r][l] = r;
+  int n = N;
+  for (int st = 1; st <= 6; ++st) {
+    const int m = (n + 1) / 2;
+    for (int i = 0; i < m; ++i) {
+      const int A = 2 * i, B = 2 * i + 1 < n ? 2 * i + 1 : 2 * i;
+      for (int l = 0; l < 64; ++l) {
+        int v = 0;
+        if (st == 1) v = l < 32 ? lab[A][l] : lab[B][l];
+        else if (st == 2) v = (l / 16) % 2 == 0 ? lab[A][l] : lab[B][l - 16];
+        else v = (l % (32 >> (st - 2))) < (16 >> (st - 2)) ? lab[A][l] : lab[B][l];
+        nl[i][l] = v;
+      }
+    }
+    for (int i = 0; i < m; ++i)
+      for (int l = 0; l < 64; ++l) lab[i][l] = nl[i][l];
+    n = m;
+  }
+  BflyMap<N> out{};
+  for (int k = 0; k < N; ++k) {
+    out.reg[k] = -1;
+    for (int r = n - 1; r >= 0; --r)
+      for (int l = 63; l >= 0; --l)
+        if (lab[r][l] == k) {
+          out.reg[k] = r;
+          out.lane[k] = l;
+        }
+  }
+  return out;
+}
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_min_u32(uint32_t v) {
+  return min(v, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, CTRL, 0xF, 0xF, false));
+}
+
+// One merge stage over n registers in place (results in r[0 .. ceil(n/2) - 1]).
+template <int ST, int N>
+__device__ __forceinline__ void bfly_stage(uint32_t (&r)[N], int n, int lane) {
+#pragma unroll
+  for (int i = 0; i < (N + 1) / 2; ++i) {
+    if (i >= (n + 1) / 2) break;
+    const uint32_t a = r[2 * i];
+    const bool pair = 2 * i + 1 < n;
+    const uint32_t b = pair ? r[2 * i + 1] : a;
+    uint32_t y;
+    if constexpr (ST == 1 || ST == 2) {
+      const auto p = ST == 1 ? __builtin_amdgcn_permlane32_swap(a, b, false, false)
+                             : __builtin_amdgcn_permlane16_swap(a, b, false, false);
+      y = min((uint32_t)p[0], (uint32_t)p[1]);
+    } else {
+      constexpr int CTRL = ST == 3 ? 0x128 : ST == 4 ? 0x141 : ST == 5 ? 0x4E : 0xB1;
+      constexpr int SPAN = 32 >> (ST - 2), HALF = SPAN / 2;  // 16/8, 8/4, 4/2, 2/1
+      // both DPP minima are taken with every lane active, before the select:
+      // left to itself the compiler may turn the select into a branch and run
+      // the second one with half the lanes off, whose values it then cannot read
+      uint32_t ma = dpp_min_u32<CTRL>(a), mb = pair ? dpp_min_u32<CTRL>(b) : ma;
+      pin(ma, mb);
+      y = (lane % SPAN) < HALF ? ma : mb;
+    }
+    r[i] = y;
+  }
+}
+
 // V pair (U then D, Eqs. DT3-DT4) of one column x and one chunk of LPS
 // disparities, optionally followed by the WTA.  A wave holds 64 / LPS segments
 // of the column, each LPS lanes wide (consecutive disparities).  FULL: every
@@ -1046,9 +1135,10 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs args, VJobs jobs) {
     // argmin over the chunk's disparities, lowest d on ties (Eq. WTA1).  The
     // aggregated costs are >= 0, so their bit patterns order like the values
     // (|.| folds a -0 onto +0); the centred integer volumes can be negative and
-    // use the sign-aware key instead.  Idle lanes hold +inf.  Pixels are
-    // reduced 8 at a time with their DPP chains interleaved; pixel k of a
-    // segment keeps its (argmin, minimum) in lane k % LPS of that segment's
+    // use the sign-aware key instead.  Idle lanes hold +inf.  64-lane
+    // segments take all their pixels' minima in one butterfly; 32-lane ones
+    // reduce 8 pixels at a time with their DPP chains interleaved.  Pixel k of
+    // a segment keeps its (argmin, minimum) in lane k % LPS of that segment's
     // lanes, in result register k / LPS, and the results leave in one store
     // per register.
     auto key = [](float v) -> uint32_t {
@@ -1065,28 +1155,52 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs args, VJobs jobs) {
       rd[r] = 0;
       rv[r] = kInf;
     }
+    if constexpr (LPS == 64) {
+      // all SEG pixels' minima at once (butterfly), then per pixel the first
+      // lane holding its minimum; pixel k's result goes to lane k % 64
+      uint32_t u[SEG], t[SEG];
 #pragma unroll
-    for (int k0 = 0; k0 < SEG; k0 += B) {
-      uint32_t v[B], m[B];
-#pragma unroll
-      for (int i = 0; i < B; ++i) {
-        const int k = min(k0 + i, SEG - 1);
-        v[i] = act ? key(c[k]) : kInf;
-        m[i] = v[i];
+      for (int k = 0; k < SEG; ++k) {
+        u[k] = act ? key(c[k]) : kInf;
+        t[k] = u[k];
       }
-      group_min_u32<B, LPS>(m);
+      bfly_stage<1>(t, SEG, lane);
+      bfly_stage<2>(t, bfly_count(SEG, 1), lane);
+      bfly_stage<3>(t, bfly_count(SEG, 2), lane);
+      bfly_stage<4>(t, bfly_count(SEG, 3), lane);
+      bfly_stage<5>(t, bfly_count(SEG, 4), lane);
+      bfly_stage<6>(t, bfly_count(SEG, 5), lane);
+      constexpr BflyMap<SEG> map = bfly_map<SEG>();
 #pragma unroll
-      for (int i = 0; i < B; ++i) {
-        const int k = k0 + i;
-        if (k < SEG && k < len) {
-          const bool mine = dloc == k % LPS;
-          if constexpr (LPS == 64) {
-            const uint32_t mk = (uint32_t)__builtin_amdgcn_readlane((int)m[i], 63);
-            const unsigned long long mask = __ballot(v[i] == mk);
-            const int db = d0 + (int)__builtin_ctzll(mask);
-            rd[k / LPS] = mine ? db : rd[k / LPS];
-            rv[k / LPS] = mine ? mk : rv[k / LPS];
-          } else {
+      for (int k = 0; k < SEG; ++k) {
+        if (k < len) {
+          const uint32_t mk = (uint32_t)__builtin_amdgcn_readlane((int)t[map.reg[k]], map.lane[k]);
+          const unsigned long long mask = __ballot(u[k] == mk);
+          const int db = d0 + (int)__builtin_ctzll(mask);
+          const bool mine = lane == k % 64;
+          rd[k / 64] = mine ? db : rd[k / 64];
+          rv[k / 64] = mine ? mk : rv[k / 64];
+        }
+      }
+    }
+    if constexpr (LPS != 64) {
+      // two segments per wave: per pixel, a DPP minimum over each half-wave,
+      // 8 pixels interleaved
+#pragma unroll
+      for (int k0 = 0; k0 < SEG; k0 += B) {
+        uint32_t v[B], m[B];
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+          const int k = min(k0 + i, SEG - 1);
+          v[i] = act ? key(c[k]) : kInf;
+          m[i] = v[i];
+        }
+        group_min_u32<B, LPS>(m);
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+          const int k = k0 + i;
+          if (k < SEG && k < len) {
+            const bool mine = dloc == k % LPS;
             const uint32_t mk0 = (uint32_t)__builtin_amdgcn_readlane((int)m[i], 31);
             const uint32_t mk1 = (uint32_t)__builtin_amdgcn_readlane((int)m[i], 63);
             const uint32_t mk = lane < 32 ? mk0 : mk1;

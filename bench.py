@@ -246,6 +246,15 @@ def main():
             del vol_s
         sweep["D%d" % dd] = row
 
+    # the paper's Method 2 window sums (integral images, rows then columns, four
+    # corners) of the pair: the per-image sums and sums of squares on their own
+    p_int = zdt.params(W, H, D, R)
+    ws_int = torch.empty(zdt.integral_workspace_size(p_int), dtype=torch.uint8, device=dev)
+    sums = [torch.empty(sh, dtype=torch.int32, device=dev) for sh in ((H, W), (H, W), (H, W + D - 1), (H, W + D - 1))]
+    ms_int = time_steps(lambda: zdt.zncc_window_sums_integral(p_int, L, Rt, *sums, ws=ws_int), max(10, args.steps // 10),
+                        3, torch)
+    del ws_int, sums
+
     # the plain FP32 per-pair form: raw cost volume, 12 unfused DT passes, WTA
     p32 = zdt.params(W, H, D, R, SIGMA_S, SIGMA_R, ITERS)
     vol = torch.empty((H, W, D), dtype=torch.float32, device=dev)
@@ -339,6 +348,7 @@ def main():
         "p99_ms_served": served["poisson"]["p99_ms"] if served else None,
         "batch": batch, "serving": served,
         "window_sweep_cost_ms": sweep,
+        "window_sums_integral_ms": round(ms_int, 4),
     }
     print(json.dumps(line))
 

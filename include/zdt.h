@@ -223,6 +223,20 @@ int zdt_autotune(const zdt_params* params, const char* cache_path, zdt_plan* cho
 int zncc_window_sums(const zdt_params* params, const uint8_t* left, const uint8_t* right, int32_t* s_l,
                      int32_t* s_ll, int32_t* s_t, int32_t* s_tt, int32_t* s_rt, void* stream);
 
+/* The same reference and target window sums by the paper's Method 2
+ * (Sec. IV-B): integral images of the border-replicated image and of its
+ * squares, integrating every row (a block-wide scan) and then every column,
+ * and each window sum from four corners.  The integrals are kept in uint32 and
+ * wrap on large images; a window's sum is below 2^31 and the four-corner
+ * difference is exact modulo 2^32, so the results equal zncc_window_sums()'s
+ * bit for bit.  Any output may be NULL; `ws` is DEVICE memory of
+ * zdt_integral_workspace_size() bytes (4-byte aligned) holding the integral
+ * images, overwritten.  W + D - 1 + 2r must not exceed 3072
+ * (ZDT_EUNSUPPORTED). */
+size_t zdt_integral_workspace_size(const zdt_params* params);
+int zncc_window_sums_integral(const zdt_params* params, const uint8_t* left, const uint8_t* right, int32_t* s_l,
+                              int32_t* s_ll, int32_t* s_t, int32_t* s_tt, void* ws, void* stream);
+
 /* Test entry for the 8-bit code of ZDT_I8 volumes (Sec. IV-C, data encoding
  * and decoding): codes[i] = encode(values[i]) and decoded[i] =
  * decode(codes[i]) for i < n, on the device.  All three are DEVICE arrays. */

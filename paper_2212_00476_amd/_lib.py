@@ -21,7 +21,7 @@ ZDT_FLAG_GUIDE_TARGET = 2
 EXPORTED = ("zdt_workspace_size", "zdt_volume_size", "zncc_cost_volume", "dt_aggregate", "wta_disparity",
             "stereo_solve", "stereo_solve_batch", "zdt_plan_candidates", "zdt_get_plan", "zdt_set_plan",
             "zdt_autotune", "zncc_window_sums", "zdt_i8_codec", "sgm_aggregate", "sgm_disparity",
-            "stereo_solve_sgm", "zdt_last_error", "zdt_profile_enable", "zdt_profile_collect", "zdt_profile_entry")
+            "stereo_solve_sgm", "zdt_integral_workspace_size", "zncc_window_sums_integral", "zdt_last_error", "zdt_profile_enable", "zdt_profile_collect", "zdt_profile_entry")
 
 
 class ZdtParams(ctypes.Structure):
@@ -80,6 +80,9 @@ def load():
     lib.zdt_i8_codec.argtypes = [P, P, P, ctypes.c_int64, P]
     F = ctypes.c_float
     lib.sgm_aggregate.argtypes = [PP, P, P, F, F, F, P]
+    lib.zdt_integral_workspace_size.argtypes = [PP]
+    lib.zdt_integral_workspace_size.restype = ctypes.c_size_t
+    lib.zncc_window_sums_integral.argtypes = [PP, P, P, P, P, P, P, P, P]
     lib.sgm_disparity.argtypes = [PP, P, P, P, F, F, F, P]
     lib.stereo_solve_sgm.argtypes = [PP, P, P, P, P, P, F, F, F, P]
     lib.zdt_last_error.restype = ctypes.c_char_p
@@ -88,7 +91,8 @@ def load():
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     for f in ("zncc_cost_volume", "dt_aggregate", "wta_disparity", "stereo_solve", "stereo_solve_batch",
               "zdt_plan_candidates", "zdt_get_plan", "zdt_set_plan", "zdt_autotune", "zncc_window_sums", "zdt_i8_codec",
-              "sgm_aggregate", "sgm_disparity", "stereo_solve_sgm", "zdt_profile_enable", "zdt_profile_collect",
+              "sgm_aggregate", "sgm_disparity", "stereo_solve_sgm", "zncc_window_sums_integral", "zdt_profile_enable",
+              "zdt_profile_collect",
               "zdt_profile_entry"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
@@ -232,3 +236,17 @@ def stereo_solve_sgm(p, left, right, disp, cost, out_sum, p1, p2, cost_scale, st
     _check("stereo_solve_sgm", load().stereo_solve_sgm(ctypes.byref(p), _ptr(left), _ptr(right), _ptr(disp),
                                                        _ptr(cost), _ptr(out_sum), float(p1), float(p2),
                                                        float(cost_scale), _stream(stream)))
+
+
+def integral_workspace_size(p):
+    return load().zdt_integral_workspace_size(ctypes.byref(p))
+
+
+def zncc_window_sums_integral(p, left, right, s_l=None, s_ll=None, s_t=None, s_tt=None, ws=None, stream=None):
+    """Window sums by integral images (the paper's Method 2); allocates the workspace if none is given."""
+    if ws is None:
+        import torch
+        ws = torch.empty(integral_workspace_size(p), dtype=torch.uint8, device=left.device)
+    _check("zncc_window_sums_integral",
+           load().zncc_window_sums_integral(ctypes.byref(p), _ptr(left), _ptr(right), _ptr(s_l), _ptr(s_ll),
+                                            _ptr(s_t), _ptr(s_tt), _ptr(ws), _stream(stream)))

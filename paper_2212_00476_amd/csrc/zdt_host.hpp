@@ -84,4 +84,10 @@ struct SgmArgs {
 };
 int dispatch_sgm(const SgmArgs& a, bool vert, bool wta, hipStream_t s);
 
+// Window sums by integral images (zdt_integral.hip): 32-bit words of one
+// integral array of image 0 (reference) or 1 (target), and the whole pass.
+size_t integral_words(int W, int H, int D, int r, int image);
+int integral_window_sums(const uint8_t* left, const uint8_t* right, int pitch, int W, int H, int D, int r,
+                         int32_t* s_l, int32_t* s_ll, int32_t* s_t, int32_t* s_tt, void* ws, hipStream_t s);
+
 }  // namespace zdt

@@ -563,6 +563,24 @@ int zncc_window_sums(const zdt_params* p, const uint8_t* left, const uint8_t* ri
   return launch_h(p, ZDT_F32, kSums, false, a, t, 1, plan_for(p), (hipStream_t)stream);
 }
 
+size_t zdt_integral_workspace_size(const zdt_params* p) {
+  if (check_params(p, "zdt_integral_workspace_size") != ZDT_OK) return 0;
+  size_t words = 0;
+  for (int im = 0; im < 2; ++im) words += 2 * integral_words(p->width, p->height, p->max_disp, p->radius, im);
+  return words * 4;
+}
+
+int zncc_window_sums_integral(const zdt_params* p, const uint8_t* left, const uint8_t* right, int32_t* s_l,
+                              int32_t* s_ll, int32_t* s_t, int32_t* s_tt, void* ws, void* stream) {
+  int rc = check_params(p, "zncc_window_sums_integral");
+  if (rc) return rc;
+  if (!left || !right) return fail(ZDT_EINVAL, "zncc_window_sums_integral: NULL image pointer");
+  if (!ws) return fail(ZDT_EINVAL, "zncc_window_sums_integral: NULL workspace");
+  if ((uintptr_t)ws & 3) return fail(ZDT_EINVAL, "zncc_window_sums_integral: workspace must be 4-byte aligned");
+  return integral_window_sums(left, right, p->pitch, p->width, p->height, p->max_disp, p->radius, s_l, s_ll, s_t,
+                              s_tt, ws, (hipStream_t)stream);
+}
+
 int dt_aggregate(const zdt_params* p, const uint8_t* guide, void* cost, double* applied_scale, void* stream) {
   int rc = check_params(p, "dt_aggregate");
   if (rc) return rc;

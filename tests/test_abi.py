@@ -101,3 +101,19 @@ def test_sgm_argument_validation_without_device():
                None) == _lib.ZDT_EINVAL
     assert lib.stereo_solve_sgm(ctypes.byref(p), None, None, None, cost, out, 18.0, 185.0, 21.0,
                                 None) == _lib.ZDT_EINVAL
+
+
+def test_integral_window_sums_validation_without_device():
+    lib = zdt.load()
+    p = zdt.params(64, 32, 16, radius=3)
+    rows = 32 + 2 * 3 + 1
+    want = 4 * 2 * (rows * (64 + 6 + 1) + rows * (64 + 15 + 6 + 1))
+    assert zdt.integral_workspace_size(p) == want
+    img, ws = ctypes.c_void_p(0x10000000), ctypes.c_void_p(0x20000000)   # never dereferenced
+    f = lib.zncc_window_sums_integral
+    assert f(ctypes.byref(p), img, img, None, None, None, None, None, None) == _lib.ZDT_EINVAL       # no workspace
+    assert f(ctypes.byref(p), None, img, None, None, None, None, ws, None) == _lib.ZDT_EINVAL        # no image
+    assert f(ctypes.byref(p), img, img, None, None, None, None, ctypes.c_void_p(0x20000002),
+             None) == _lib.ZDT_EINVAL                                                               # misaligned
+    wide = zdt.params(1920, 8, 1200, radius=7)        # 1920 + 1199 + 14 padded target columns
+    assert f(ctypes.byref(wide), img, img, None, None, None, None, ws, None) == _lib.ZDT_EUNSUPPORTED

@@ -80,14 +80,23 @@ bool prof_begin(ProfRec& rec, hipStream_t s) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     if (!g_prof_on) return false;
   }
+  rec.start = rec.stop = nullptr;
   if (hipEventCreate(&rec.start) != hipSuccess || hipEventCreate(&rec.stop) != hipSuccess ||
-      hipEventRecord(rec.start, s) != hipSuccess)
+      hipEventRecord(rec.start, s) != hipSuccess) {
+    if (rec.start) (void)hipEventDestroy(rec.start);
+    if (rec.stop) (void)hipEventDestroy(rec.stop);
+    rec.start = rec.stop = nullptr;
     return false;
+  }
   return true;
 }
 
 void prof_end(ProfRec& rec, hipStream_t s) {
-  if (hipEventRecord(rec.stop, s) != hipSuccess) return;
+  if (hipEventRecord(rec.stop, s) != hipSuccess) {
+    (void)hipEventDestroy(rec.start);
+    (void)hipEventDestroy(rec.stop);
+    return;
+  }
   std::lock_guard<std::mutex> lk(g_prof_mu);
   g_prof_pending.push_back(rec);
 }

@@ -239,10 +239,13 @@ __device__ __forceinline__ float carry_in(const float* B, const float* A, int se
 //   WH[W+1]       W_L(x) for x in [0, W]; WH[0] = WH[W] = 0.
 //   EX, EX2 [16*64], EXS, EXS2 [kMaxSegs]   segment carries.
 //   GI, GO [W]    gains of the row before and after the pass pair (FP16
-//                 working volumes only).
+//                 working volumes only); after the pair's gain line is done,
+//                 GO holds the output scale factors 2^(kGainBias - e) instead.
+//   SI [W]        input scale factors 2^(e - kGainBias) of the stored input
+//                 (FP16 H pairs over a stored volume only).
 // ---------------------------------------------------------------------------
 struct HLayout {
-  int nLP, nTP, nTS, oLP, oLS, oLI, oTP, oTS, oTI, oWH, oEX, oEXS, oEX2, oEXS2, oGI, oGO, words;
+  int nLP, nTP, nTS, oLP, oLS, oLI, oTP, oTS, oTI, oWH, oEX, oEXS, oEX2, oEXS2, oGI, oGO, oSI, words;
 };
 
 __host__ __device__ constexpr HLayout h_layout(int W, int R, int LPS, int pad, bool zncc, bool dt, bool scaled) {
@@ -270,6 +273,8 @@ __host__ __device__ constexpr HLayout h_layout(int W, int R, int LPS, int pad, b
     if (scaled) o += W + pad;  // FP16 working volume: the row's gains before and after the pair
     L.oGO = o;
     if (scaled) o += W + pad;
+    L.oSI = o;
+    if (scaled && !zncc) o += W + pad;
   }
   L.words = o;
   return L;
@@ -492,8 +497,15 @@ __device__ __forceinline__ void block_min_u32(uint32_t (&m)[B]) {
 #undef ZDT_STAGE
 }
 
-// floor(log2 g) for a normal positive g (the gain G >= 1).
-__device__ __forceinline__ int gain_exp(float g) { return (int)(__float_as_uint(g) >> 23) - 127; }
+// Scale factors of a gain G >= 1 with e = floor(log2 G): 2^(e - kGainBias) to
+// decode a stored value and 2^(kGainBias - e) to encode one.  Multiplying by
+// them equals ldexp by the same exponents, bit for bit.
+__device__ __forceinline__ float gain_scale_in(float g) {
+  return __uint_as_float(((__float_as_uint(g) >> 23) - kGainBias) << 23);
+}
+__device__ __forceinline__ float gain_scale_out(float g) {
+  return __uint_as_float((uint32_t)(254 + kGainBias - (int)(__float_as_uint(g) >> 23)) << 23);
+}
 
 // Exclusive scan over the 64 lanes, in lane order, of the affine maps
 // c -> A c + B: the composition of the maps of lanes 0..l-1 (identity for lane
@@ -633,9 +645,14 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
   if constexpr (kDT) stage_row_weights(a, (float*)(smem + lay.oWH), y);
   float* GI = (float*)(smem + lay.oGI);
   float* GO = (float*)(smem + lay.oGO);
+  float* SI = (float*)(smem + lay.oSI);
   if constexpr (kHalf && MODE == kHPair) {
     const float* gr = a.g_in + (size_t)y * W;  // gains of the stored input row
-    for (int x = threadIdx.x; x < W; x += blockDim.x) GI[x] = gr[x];
+    for (int x = threadIdx.x; x < W; x += blockDim.x) {
+      const float g = gr[x];
+      GI[x] = g;
+      SI[x] = gain_scale_in(g);
+    }
   }
   if constexpr (kInt && MODE == kCostHPair) {
     const float* rr = a.ref0 + (size_t)y * W;  // the row's raw cost at d = 0
@@ -710,8 +727,11 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
       // start their segments meanwhile and read it only after two barriers
       if (wave == (int)(blockDim.x / kWave) - 1) {
         line_pair_gain(MODE == kHPair ? GI : nullptr, GO, WH, W);
-        if (chunk == 0)
-          for (int x = lane; x < W; x += kWave) a.g_out[(size_t)y * W + x] = GO[x];
+        for (int x = lane; x < W; x += kWave) {
+          const float g = GO[x];
+          if (chunk == 0) a.g_out[(size_t)y * W + x] = g;
+          GO[x] = gain_scale_out(g);
+        }
       }
     }
     const float* wp = WH + x0;  // W_L at x0 + k; padded past the row
@@ -766,11 +786,11 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
         if constexpr (kInt) c[k] *= a.in_scale;
       }
       __builtin_amdgcn_sched_barrier(0);
-      const float* gi = GI + x0;  // gains of the stored input at x0 + k
+      const float* si = SI + x0;  // input scale factors at x0 + k
 #pragma unroll
       for (int k = 0; k < SEG; ++k) {
         const bool in = k < len;
-        if constexpr (scaled) c[k] = ldexpf(c[k], gain_exp(gi[k]) - kGainBias);
+        if constexpr (scaled) c[k] *= si[k];
         const float w = wp[k];
         ell = in ? fmaf(w, ell, c[k]) : ell;
         P = in ? P * w : P;
@@ -814,11 +834,10 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
       next = in ? cr : next;
       step_fence(SEG - 1 - k, next);
     }
-    const float* go = GO + x0;  // gains of the output at x0 + k
+    const float* so = GO + x0;  // output scale factors at x0 + k
 #pragma unroll
     for (int k = 0; k < SEG; ++k) {
-      float v = c[k] * a.out_scale;
-      if constexpr (scaled) v = ldexpf(v, kGainBias - gain_exp(go[k]));
+      const float v = scaled ? c[k] * so[k] : c[k] * a.out_scale;
       if (k < len && active) Elem<T>::bstore(vrs, voff, step_soff(k), v);
     }
   }
@@ -859,7 +878,7 @@ struct VJobs {
 // EXS/EXS2 [kMaxSegs], and for the FP16 working volume GI, GO [H + SEG], the
 // column's gains before and after the pair.
 __host__ __device__ inline int v_lds_words(int H, int SEG, bool scaled) {
-  return (H + 1 + SEG) + 2 * (kMaxWaves * kWave + kMaxSegs) + (scaled ? 2 * (H + SEG) : 0);
+  return (H + 1 + SEG) + 2 * (kMaxWaves * kWave + kMaxSegs) + (scaled ? 3 * (H + SEG) : 0);
 }
 
 // Order-preserving 32-bit key of a float (-0 folded onto +0) and its inverse.
@@ -1027,9 +1046,14 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs args, VJobs jobs) {
   float* EX2 = EXS + kMaxSegs;
   float* EXS2 = EX2 + kMaxWaves * kWave;
   float* GI = EXS2 + kMaxSegs;
-  float* GO = GI + (H + SEG);
+  float* GO = GI + (H + SEG);  // gains, then output scale factors (see the H pass)
+  float* SI = GO + (H + SEG);  // input scale factors
   if constexpr (kHalf)
-    for (int y = threadIdx.x; y < H; y += blockDim.x) GI[y] = a.g_in[(size_t)y * W + x];
+    for (int y = threadIdx.x; y < H; y += blockDim.x) {
+      const float g = a.g_in[(size_t)y * W + x];
+      GI[y] = g;
+      SI[y] = gain_scale_in(g);
+    }
   for (int y = threadIdx.x; y <= H; y += blockDim.x)
     WV[y] = (y >= 1 && y < H) ? dt_weight(a.guide[(size_t)y * a.pitch + x], a.guide[(size_t)(y - 1) * a.pitch + x],
                                           a.inv_sigma_s, a.range_coef)
@@ -1046,11 +1070,14 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs args, VJobs jobs) {
     // the column's gain after this pair, by the last wave (read after two barriers)
     if (wave == (int)(blockDim.x / kWave) - 1) {
       line_pair_gain(GI, GO, WV, H);
-      if (chunk == 0)
-        for (int y = lane; y < H; y += kWave) a.g_out[(size_t)y * W + x] = GO[y];
+      for (int y = lane; y < H; y += kWave) {
+        const float g = GO[y];
+        if (chunk == 0) a.g_out[(size_t)y * W + x] = g;
+        GO[y] = gain_scale_out(g);
+      }
     }
   }
-  const float* gi = GI + y0;  // gains of the stored input at y0 + k
+  const float* si = SI + y0;  // input scale factors at y0 + k
   const float* wp = WV + y0;  // W_U at y0 + k; padded past the column
   // per-lane offset: the disparity, plus the segment's first row when the two
   // halves of a wave hold different segments; per-step offset: the row step
@@ -1073,7 +1100,7 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs args, VJobs jobs) {
   for (int k = 0; k < SEG; ++k) {
     const bool in = k < len;
     const float w = wp[k];
-    if constexpr (scaled) c[k] = ldexpf(c[k], gain_exp(gi[k]) - kGainBias);
+    if constexpr (scaled) c[k] *= si[k];
     ell = in ? fmaf(w, ell, c[k]) : ell;
     P = in ? P * w : P;
     step_fence(k, ell, P);
@@ -1124,11 +1151,10 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs args, VJobs jobs) {
     step_fence(SEG - 1 - k, next);
   }
   if constexpr (!WTA) {
-    const float* go = GO + y0;  // gains of the output at y0 + k
+    const float* so = GO + y0;  // output scale factors at y0 + k
 #pragma unroll
     for (int k = 0; k < SEG; ++k) {
-      float v = c[k] * a.out_scale;
-      if constexpr (scaled) v = ldexpf(v, kGainBias - gain_exp(go[k]));
+      const float v = scaled ? c[k] * so[k] : c[k] * a.out_scale;
       if (k < len && act) Elem<T>::bstore(vrs, voff, step_off(k), v);
     }
   } else {

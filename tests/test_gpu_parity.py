@@ -516,3 +516,47 @@ def test_integer_volumes_paper_configuration(dtype):
     mism_valid = (disp[valid] != o_disp[valid]).mean()
     note(f"  paper configuration dtype={dtype}: mismatch {100 * mism:.3f} % (valid region {100 * mism_valid:.3f} %)")
     assert mism <= 0.25
+
+
+def _random_cases(n, seed=2024):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        W, H = int(rng.integers(1, 301)), int(rng.integers(1, 151))
+        D, r = int(rng.integers(1, 161)), int(rng.integers(0, 8))
+        sigma_s = float(rng.uniform(2.0, 40.0))
+        sigma_r = float(rng.choice([0.05, 0.2, np.inf]))
+        iters = int(rng.integers(0, 4))
+        flags = zdt.ZDT_FLAG_GUIDE_TARGET if rng.random() < 0.3 else 0
+        out.append((W, H, D, r, round(sigma_s, 3), sigma_r, iters, flags))
+    return out
+
+
+RANDOM = _random_cases(16)
+
+
+@pytest.mark.parametrize("case", RANDOM, ids=["%dx%d_d%d_r%d_s%g_%g_i%d_g%d" % c for c in RANDOM])
+def test_random_shapes_and_parameters_end_to_end(case):
+    """Seeded random shapes and parameters, FP32 end to end.  Bar: the DT bound
+    for this sigma_s and sweep count, 2 x (4 I) x 2^-24 x 1/(1 - K) relative to
+    the pixel's largest aggregated cost (K = exp(-1/sigma_s)); with I = 0 the
+    raw-cost bar (1e-5, doubled for the two sides of a near-tie)."""
+    W, H, D, r, sigma_s, sigma_r, iters, flags = case
+    note("random case %s" % (case,))
+    k = min(D - 1, max(1, D // 3))
+    pr = scenes.bands_pair(W=W, H=H, D=max(D, 2), seed=W * 7 + H, band_disps=tuple(sorted({0, k})))
+    p = zdt.params(W, H, D, r, sigma_s=sigma_s, sigma_r=sigma_r, dt_iters=iters, flags=flags)
+    solver = zdt.Solver(p)
+    disp = host(solver(dev(pr.left), dev(pr.right)))
+    torch.cuda.synchronize()
+    _, cagg = oracle.stereo_solve(pr.left, pr.right, D, r, sigma_s, sigma_r, iters,
+                                  guide_target=bool(flags & zdt.ZDT_FLAG_GUIDE_TARGET), keep_volume=True)
+    picked = np.take_along_axis(cagg, disp[:, :, None].astype(np.int64), axis=2)[:, :, 0]
+    slack = picked - cagg.min(axis=2)
+    if iters == 0:
+        tol = 2e-5 * np.ones_like(slack)
+    else:
+        gain = 1.0 / -np.expm1(-1.0 / sigma_s)
+        tol = 2 * (4 * iters) * 2.0 ** -24 * gain * np.abs(cagg).max(axis=2)
+    assert disp.min() >= 0 and disp.max() < D
+    assert np.all(slack <= tol), (slack - tol).max()

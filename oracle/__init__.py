@@ -58,6 +58,8 @@ def _load():
         lib.oracle_wta.argtypes = [P, I, I, I, P]
         lib.oracle_stereo_solve.argtypes = [P, P, I, I, I, I, I, Dbl, Dbl, I, I, P, P]
         lib.oracle_sgm_aggregate.argtypes = [P, I, I, I, Dbl, Dbl, Dbl, P]
+        lib.oracle_int_solve.argtypes = [P, P, I, I, I, I, I, Dbl, Dbl, I, I, Dbl, I, P, P]
+        lib.oracle_int_solve.restype = ctypes.c_int
         lib.oracle_sgm_aggregate.restype = ctypes.c_int
         lib.oracle_i8_encode.argtypes = [ctypes.c_int16]
         lib.oracle_i8_encode.restype = ctypes.c_uint8
@@ -189,6 +191,21 @@ def stereo_solve(left, right, D, r, sigma_s, sigma_r, iters, guide_target=False,
     _check(_load().oracle_stereo_solve(_ptr(L), _ptr(R), W, W, H, D, r, float(sigma_s), float(sigma_r),
                                        int(iters), int(bool(guide_target)),
                                        _ptr(vol) if vol is not None else None, _ptr(disp)), "stereo_solve")
+    return (disp, vol) if keep_volume else disp
+
+
+def int_solve(left, right, D, r, sigma_s, sigma_r, iters, T=21.0, code8=False, guide_target=False,
+              keep_volume=False):
+    """The integer-volume path (Sec. IV-C): centred cost, DT pass pairs with the
+    stored state quantized to int16 (or its 8-bit code) between pairs, WTA.
+    Returns disp [H][W] int32, and the last pair's output if asked."""
+    L, R = _u8(left), _u8(right)
+    H, W = L.shape
+    disp = np.empty((H, W), np.int32)
+    vol = np.empty((H, W, D), np.float64) if keep_volume else None
+    _check(_load().oracle_int_solve(_ptr(L), _ptr(R), W, W, H, D, r, float(sigma_s), float(sigma_r), int(iters),
+                                    int(bool(guide_target)), float(T), int(bool(code8)),
+                                    _ptr(vol) if vol is not None else None, _ptr(disp)), "int_solve")
     return (disp, vol) if keep_volume else disp
 
 

@@ -299,6 +299,86 @@ int16_t oracle_i8_decode(uint8_t c) {
 }
 
 /* ---------------------------------------------------------------------------
+ * The paper's narrow integer volumes (Sec. IV-C) as a whole path.  The cost
+ * 1 - ZNCC is made nearly zero-mean by subtracting its slice at d_arb = 0
+ * (Eq. DT_new; the recursions are linear and map a zero slice to zero, so the
+ * subtraction is done once, before the first pass).  The DT then runs as pass
+ * pairs, L then R along rows and U then D along columns, and the state stored
+ * between two pairs is quantized: v becomes q = sat16(round(T v)), rounding
+ * halves to even; with code8 the stored byte is q's 8-bit code, so q becomes
+ * decode(encode(q)); the next pair reads q / T.  The last pair's output is not
+ * stored: it goes to the WTA as is.  Only iters >= 1 is defined.
+ * final_hwd (nullable) receives that last output.
+ * ------------------------------------------------------------------------- */
+static double quantize16(double v, double T, int code8) {
+  double q = nearbyint(T * v); /* default rounding mode: to nearest, ties to even */
+  if (q > 32767.0) q = 32767.0;
+  if (q < -32768.0) q = -32768.0;
+  int16_t s = (int16_t)q;
+  if (code8) s = oracle_i8_decode(oracle_i8_encode(s));
+  return (double)s / T;
+}
+
+static void h_pair(double* c, int W, int H, const double* wh) {
+  for (int y = 0; y < H; ++y) {
+    double* row = c + (ptrdiff_t)y * W;
+    const double* w = wh + (ptrdiff_t)y * W;
+    for (int x = 1; x < W; ++x) row[x] += w[x] * row[x - 1];
+    for (int x = W - 2; x >= 0; --x) row[x] += w[x + 1] * row[x + 1];
+  }
+}
+
+static void v_pair(double* c, int W, int H, const double* wv) {
+  for (int x = 0; x < W; ++x) {
+    for (int y = 1; y < H; ++y) c[(ptrdiff_t)y * W + x] += wv[(ptrdiff_t)y * W + x] * c[(ptrdiff_t)(y - 1) * W + x];
+    for (int y = H - 2; y >= 0; --y)
+      c[(ptrdiff_t)y * W + x] += wv[(ptrdiff_t)(y + 1) * W + x] * c[(ptrdiff_t)(y + 1) * W + x];
+  }
+}
+
+int oracle_int_solve(const uint8_t* L, const uint8_t* R, int pitch, int W, int H, int D, int r, double sigma_s,
+                     double sigma_r, int iters, int guide_target, double T, int code8, double* final_hwd,
+                     int32_t* disp_hw) {
+  if (W < 1 || H < 1 || D < 1 || r < 0 || iters < 1 || pitch < W || !(T > 0.0)) return -1;
+  const size_t np = (size_t)W * H;
+  double* c0 = (double*)malloc(np * sizeof(double));
+  double* c = (double*)malloc(np * sizeof(double));
+  double* best = (double*)malloc(np * sizeof(double));
+  double* wh = (double*)malloc(np * sizeof(double));
+  double* wv = (double*)malloc(np * sizeof(double));
+  int rc = -2;
+  if (c0 && c && best && wh && wv) {
+    rc = oracle_dt_weights(guide_target ? R : L, pitch, W, H, sigma_s, sigma_r, wh, wv);
+    if (rc == 0) rc = oracle_zncc_cost_slice(L, R, pitch, W, H, r, 0, c0);
+    for (int d = 0; rc == 0 && d < D; ++d) {
+      rc = oracle_zncc_cost_slice(L, R, pitch, W, H, r, d, c);
+      if (rc) break;
+      for (size_t p = 0; p < np; ++p) c[p] -= c0[p];
+      for (int it = 0; it < iters; ++it) {
+        h_pair(c, W, H, wh);
+        for (size_t p = 0; p < np; ++p) c[p] = quantize16(c[p], T, code8);
+        v_pair(c, W, H, wv);
+        if (it + 1 < iters)
+          for (size_t p = 0; p < np; ++p) c[p] = quantize16(c[p], T, code8);
+      }
+      for (size_t p = 0; p < np; ++p) {
+        if (final_hwd) final_hwd[p * D + d] = c[p];
+        if (d == 0 || c[p] < best[p]) { /* strict: the lowest d wins ties */
+          best[p] = c[p];
+          disp_hw[p] = d;
+        }
+      }
+    }
+  }
+  free(wv);
+  free(wh);
+  free(best);
+  free(c);
+  free(c0);
+  return rc;
+}
+
+/* ---------------------------------------------------------------------------
  * Semi-global matching over four paths (the paper's system S1 combines its
  * ZNCC with SGM, P1 = 18 and P2 = 185 on costs multiplied by T, Sec. V-D).
  * Along a path r through pixels p_0, p_1, ...:

@@ -350,3 +350,69 @@ def test_sgm_without_penalties_is_four_times_the_cost():
     assert np.array_equal(oracle.sgm_aggregate(c, 0.0, 0.0, 3.0), 4.0 * (3.0 * c))
     one = rng.uniform(0.0, 2.0, (1, 1, 7))
     assert np.array_equal(oracle.sgm_aggregate(one, 18.0, 185.0, 21.0), 4.0 * (21.0 * one))
+
+
+# ------------------------------------------- integer volumes (Sec. IV-C) path
+def test_int_path_is_the_float_path_on_centred_costs_up_to_propagated_rounding():
+    """Each quantization between pass pairs moves a value by at most 1/(2T)
+    (no value here comes near saturation), and a later pass pair amplifies a
+    perturbation by at most G = (1+K)/(1-K), K = exp(-1/sigma_s).  So after I
+    sweeps (2I - 1 quantizations) the result is within
+    sum_{j=1}^{2I-1} G^j / (2T) of the float DT of the cost minus its d = 0
+    slice; with I = 1 that is G / (2T)."""
+    pr = scenes.bands_pair(W=40, H=24, D=12, seed=2, band_disps=(2, 7))
+    D, r, sr, T = 12, 2, 52.0 / 255.0, 21.0
+    c = oracle.zncc_cost(pr.left, pr.right, D, r)
+    c = c - c[:, :, :1]
+    for ss, iters in ((5.0, 1), (2.0, 1), (2.0, 2)):  # the stored states stay far from saturation
+        K = np.exp(-1.0 / ss)
+        G = (1 + K) / (1 - K)
+        wh, wv = oracle.dt_weights(pr.left, ss, sr)
+        _, got = oracle.int_solve(pr.left, pr.right, D, r, ss, sr, iters, T=T, keep_volume=True)
+        want = oracle.dt_aggregate(c, wh, wv, iters)
+        assert np.abs(want).max() * T < 32767 / 4
+        bound = sum(G ** j for j in range(1, 2 * iters)) / (2 * T)
+        err = np.abs(got - want).max()
+        assert 0 < err <= bound + 1e-9, (iters, err, bound)
+
+
+def _quantized(v, T, code8):
+    q = np.clip(np.rint(T * v), -32768, 32767).astype(np.int16)
+    if code8:
+        q = oracle.i8_decode(oracle.i8_encode(q))
+    return q.astype(np.float64) / T
+
+
+@pytest.mark.parametrize("code8", [False, True])
+def test_int_path_without_aggregation_is_the_quantizer(code8):
+    """With sigma_s = 1e-3 every DT weight exp(-1000 - ...) is exactly 0 in
+    double precision, so each pass pair is the identity and the result is the
+    centred cost quantized once (quantizing a stored value again changes
+    nothing).  T = 1e7 drives the larger values into saturation at both ends."""
+    pr = scenes.bands_pair(W=30, H=12, D=9, seed=6, band_disps=(1, 5))
+    D, r = 9, 1
+    c = oracle.zncc_cost(pr.left, pr.right, D, r)
+    c = c - c[:, :, :1]
+    wh, _ = oracle.dt_weights(pr.left, 1e-3, 0.2)
+    assert not wh.any()
+    for T in (21.0, 3.7, 1e7):
+        for iters in (1, 2, 3):
+            _, got = oracle.int_solve(pr.left, pr.right, D, r, 1e-3, 0.2, iters, T=T, code8=code8,
+                                      keep_volume=True)
+            assert np.array_equal(got, _quantized(c, T, code8)), (T, iters)
+    _, sat = oracle.int_solve(pr.left, pr.right, D, r, 1e-3, 0.2, 1, T=1e7, code8=code8, keep_volume=True)
+    q = np.rint(sat * 1e7)
+    if code8:   # the 8-bit code keeps negative values only
+        assert (q == -32768).any() and np.all(q <= 0)
+    else:       # both ends of the int16 range are reached
+        assert (q == 32767).any() and (q == -32768).any()
+
+
+def test_int_path_leaves_the_last_pair_unquantized():
+    """The last pass pair's output goes to the WTA as is: it is not a multiple of
+    1/T, while a single sweep's only stored state (after the H pair) is."""
+    pr = scenes.bands_pair(W=48, H=30, D=10, seed=3, band_disps=(2, 6))
+    D, r, ss, sr, T = 10, 1, 5.0, 52.0 / 255.0, 21.0
+    _, got = oracle.int_solve(pr.left, pr.right, D, r, ss, sr, 1, T=T, keep_volume=True)
+    frac = np.abs(got * T - np.rint(got * T))
+    assert (frac > 1e-6).mean() > 0.5

@@ -48,6 +48,7 @@ struct IntegralArgs {
 
 __global__ __launch_bounds__(kScanThreads) void integral_rows_kernel(IntegralArgs a) {
   __shared__ uint32_t wtot[2][kScanThreads / kWave];
+  __shared__ uint32_t line[2][kScanThreads * kScanItems];  // the scanned row, for coalesced stores
   const int im = blockIdx.y;
   const int py = blockIdx.x;  // padded row, 0 .. H+2r-1
   const int n = a.cols[im];
@@ -83,15 +84,13 @@ __global__ __launch_bounds__(kScanThreads) void integral_rows_kernel(IntegralArg
   uint32_t* oq = a.sq[im] + (size_t)(py + 1) * stride;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
-    const int j = j0 + i;
-    if (j < n) {
-      os[j + 1] = v[i] + off;
-      oq[j + 1] = q[i] + off2;
-    }
+    line[0][j0 + i] = v[i] + off;
+    line[1][j0 + i] = q[i] + off2;
   }
-  if (t == 0) {
-    os[0] = 0;
-    oq[0] = 0;
+  __syncthreads();
+  for (int j = t; j <= n; j += kScanThreads) {
+    os[j] = j ? line[0][j - 1] : 0u;
+    oq[j] = j ? line[1][j - 1] : 0u;
   }
   if (py == 0)  // the zero row of the integral
     for (int j = t; j <= n; j += kScanThreads) {
@@ -118,16 +117,31 @@ __global__ __launch_bounds__(kWave * kColWaves) void integral_cols_kernel(Integr
   const int rows = a.H + 2 * a.r;  // integral rows 1 .. rows
   const int per = (rows + kColWaves - 1) / kColWaves;
   const int i0 = 1 + wave * per, i1 = min(i0 + per, rows + 1);
+  // 8 rows at a time: the loads of a group are independent and in flight together
+  constexpr int G = 8;
   uint32_t s = 0;
-  for (int i = i0; i < i1; ++i) s += b[(size_t)i * stride];
+  for (int g = i0; g < i1; g += G) {
+    uint32_t v[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) v[k] = g + k < i1 ? b[(size_t)(g + k) * stride] : 0u;
+#pragma unroll
+    for (int k = 0; k < G; ++k) s += v[k];
+  }
   tot[wave][lane] = s;
   __syncthreads();
   uint32_t acc = 0;
   for (int w = 0; w < wave; ++w) acc += tot[w][lane];
   if (!on) return;
-  for (int i = i0; i < i1; ++i) {
-    acc += b[(size_t)i * stride];
-    b[(size_t)i * stride] = acc;
+  for (int g = i0; g < i1; g += G) {
+    uint32_t v[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) v[k] = g + k < i1 ? b[(size_t)(g + k) * stride] : 0u;
+#pragma unroll
+    for (int k = 0; k < G; ++k)
+      if (g + k < i1) {
+        acc += v[k];
+        b[(size_t)(g + k) * stride] = acc;
+      }
   }
 }
 

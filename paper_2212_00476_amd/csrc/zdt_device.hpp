@@ -251,9 +251,11 @@ struct HLayout {
 __host__ __device__ constexpr HLayout h_layout(int W, int R, int LPS, int pad, bool zncc, bool dt, bool scaled) {
   HLayout L{};
   const int NP = packs_of(R);
-  L.nLP = W + 2 * R + pad;
+  // packed columns: a row's W + 2R (reference) or nTS + 2R (target) columns,
+  // then padding (at least the kStatRun - 1 columns a statistics run reads past them)
+  L.nLP = W + 2 * R + (pad > 3 ? pad : 3);
   L.nTS = W + LPS - 1;
-  L.nTP = L.nTS + 2 * R + pad;
+  L.nTP = L.nTS + 2 * R + (pad > 3 ? pad : 3);
   int o = 0;
   if (zncc) {
     L.oLP = o; o += NP * L.nLP;
@@ -326,19 +328,69 @@ __device__ __forceinline__ float dt_weight(int ga, int gb, float inv_sigma_s, fl
   return expf(-(inv_sigma_s + (float)abs(ga - gb) * range_coef));
 }
 
+// Window sums of one image at kStatRun consecutive positions: the column sums
+// (of I and I^2, by dot4 over the packed rows) of the kStatRun + 2R columns
+// involved are formed once and the window slides over them.  P holds packed
+// columns pack-major with stride np; position p covers columns p .. p+2R.
+constexpr int kStatRun = 4;
+static_assert(kStatRun - 1 <= 3, "packed-column padding of h_layout");
+template <int R>
+__device__ __forceinline__ void window_run(const uint32_t* P, int np, int p0, uint32_t (&s)[kStatRun],
+                                           uint32_t (&ss)[kStatRun]) {
+  constexpr int NP = packs_of(R);
+  constexpr int NW = 2 * R + 1;
+  constexpr int NC = kStatRun + 2 * R;
+  uint32_t cs[NC], css[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    const int col = p0 + j;  // up to kStatRun - 1 columns past the row: padding of the array
+    cs[j] = 0;
+    css[j] = 0;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const uint32_t v = P[k * np + col];
+      cs[j] = __builtin_amdgcn_udot4(v, 0x01010101u, cs[j], false);
+      css[j] = __builtin_amdgcn_udot4(v, v, css[j], false);
+    }
+  }
+  uint32_t a = 0, b = 0;
+#pragma unroll
+  for (int j = 0; j < NW; ++j) {
+    a += cs[j];
+    b += css[j];
+  }
+  s[0] = a;
+  ss[0] = b;
+#pragma unroll
+  for (int i = 1; i < kStatRun; ++i) {
+    a += cs[i + 2 * R] - cs[i - 1];
+    b += css[i + 2 * R] - css[i - 1];
+    s[i] = a;
+    ss[i] = b;
+  }
+}
+
 // Stage the packed window columns and the per-position window statistics of
 // both images for row y and disparity chunk d0 (reads the 2R+1 image rows once).
 template <int R, int LPS>
 __device__ void stage_zncc(const HArgs& a, const HLayout& lay, uint32_t* smem, int y, int d0, int mode) {
   constexpr int NP = packs_of(R);
-  constexpr int N = (2 * R + 1) * (2 * R + 1);
+  constexpr int NW = 2 * R + 1;
+  constexpr int N = NW * NW;
   constexpr int P = LPS - 1;
   const int tid = threadIdx.x, nt = blockDim.x, W = a.W, H = a.H;
   uint32_t* LP = smem + lay.oLP;
   uint32_t* TP = smem + lay.oTP;
-  int rows_off[NP * 4];
+  const uint8_t* lrow[NW];
+  const uint8_t* trow[NW];
 #pragma unroll
-  for (int q = 0; q < NP * 4; ++q) rows_off[q] = (q < 2 * R + 1) ? clampi(y - R + q, 0, H - 1) * a.pitch : -1;
+  for (int q = 0; q < NW; ++q) {
+    const size_t off = (size_t)clampi(y - R + q, 0, H - 1) * a.pitch;
+    lrow[q] = a.left + off;
+    trow[q] = a.right + off;
+  }
+  // pack j of a column holds rows 4j .. 4j+3 of the window, one byte each
+  // (bytes past the window's last row are zero)
   for (int i = tid; i < W + 2 * R; i += nt) {
     const int col = clampi(i - R, 0, W - 1);
 #pragma unroll
@@ -346,7 +398,7 @@ __device__ void stage_zncc(const HArgs& a, const HLayout& lay, uint32_t* smem, i
       uint32_t p = 0;
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        if (rows_off[4 * k + j] >= 0) p |= (uint32_t)a.left[rows_off[4 * k + j] + col] << (8 * j);
+        if (4 * k + j < NW) p |= (uint32_t)lrow[4 * k + j][col] << (8 * j);
       LP[k * lay.nLP + i] = p;
     }
   }
@@ -357,7 +409,7 @@ __device__ void stage_zncc(const HArgs& a, const HLayout& lay, uint32_t* smem, i
       uint32_t p = 0;
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        if (rows_off[4 * k + j] >= 0) p |= (uint32_t)a.right[rows_off[4 * k + j] + col] << (8 * j);
+        if (4 * k + j < NW) p |= (uint32_t)trow[4 * k + j][col] << (8 * j);
       TP[k * lay.nTP + i] = p;
     }
   }
@@ -366,47 +418,45 @@ __device__ void stage_zncc(const HArgs& a, const HLayout& lay, uint32_t* smem, i
   float* LI = (float*)(smem + lay.oLI);
   int32_t* TS = (int32_t*)(smem + lay.oTS);
   float* TI = (float*)(smem + lay.oTI);
-  // reference statistics at x: columns x-R..x+R are LP entries x .. x+2R
-  for (int x = tid; x < W; x += nt) {
-    uint32_t s = 0, ss = 0;
+  // Runs of kStatRun positions: the first nrl threads take the reference
+  // positions x (columns x-R..x+R are LP entries x .. x+2R), the next nrt the
+  // target positions t, i.e. x' = t - P - d0 (TP entries t .. t+2R).
+  const int nrl = (W + kStatRun - 1) / kStatRun;
+  const int nrt = (lay.nTS + kStatRun - 1) / kStatRun;
+  for (int u = tid; u < nrl + nrt; u += nt) {
+    const bool ref = u < nrl;
+    const int p0 = (ref ? u : u - nrl) * kStatRun;
+    uint32_t s[kStatRun], ss[kStatRun];
+    window_run<R>(ref ? LP : TP, ref ? lay.nLP : lay.nTP, p0, s, ss);
 #pragma unroll
-    for (int i = 0; i <= 2 * R; ++i)
-#pragma unroll
-      for (int k = 0; k < NP; ++k) {
-        const uint32_t p = LP[k * lay.nLP + x + i];
-        s = __builtin_amdgcn_udot4(p, 0x01010101u, s, false);
-        ss = __builtin_amdgcn_udot4(p, p, ss, false);
-      }
-    const int v = (int)(__umul24(N, ss) - __umul24(s, s));
-    LS[x] = (int)s;
-    LI[x] = v > 0 ? 1.0f / sqrtf((float)v) : 0.0f;
-    if (mode == kSums && blockIdx.x == 0) {
-      if (a.s_l) a.s_l[(size_t)y * W + x] = (int)s;
-      if (a.s_ll) a.s_ll[(size_t)y * W + x] = (int)ss;
-    }
-  }
-  // target statistics at x' = t - P - d0: columns x'-R..x'+R are TP entries t .. t+2R
-  for (int t = tid; t < lay.nTS; t += nt) {
-    uint32_t s = 0, ss = 0;
-#pragma unroll
-    for (int i = 0; i <= 2 * R; ++i)
-#pragma unroll
-      for (int k = 0; k < NP; ++k) {
-        const uint32_t p = TP[k * lay.nTP + t + i];
-        s = __builtin_amdgcn_udot4(p, 0x01010101u, s, false);
-        ss = __builtin_amdgcn_udot4(p, p, ss, false);
-      }
-    const int v = (int)(__umul24(N, ss) - __umul24(s, s));
-    TS[t] = (int)s;
-    TI[t] = v > 0 ? 1.0f / sqrtf((float)v) : 0.0f;
-    if (mode == kSums) {
-      // each x' in [-(D-1), W-1] is written by exactly one chunk
-      const int xe = t - P - d0;
-      const bool own = (blockIdx.x == 0) ? (xe >= -P) : (xe <= -d0);
-      if (own && xe >= -(a.D - 1) && xe <= W - 1) {
-        const size_t idx = (size_t)y * (W + a.D - 1) + xe + a.D - 1;
-        if (a.s_t) a.s_t[idx] = (int)s;
-        if (a.s_tt) a.s_tt[idx] = (int)ss;
+    for (int i = 0; i < kStatRun; ++i) {
+      const int p = p0 + i;
+      const int v = (int)(__umul24(N, ss[i]) - __umul24(s[i], s[i]));
+      // 1/sqrt(v) by the hardware reciprocal square root (within 1 ulp); zero
+      // for a flat window, whose cost is then 1 at every disparity
+      const float inv = v > 0 ? __builtin_amdgcn_rsqf((float)v) : 0.0f;
+      if (ref) {
+        if (p < W) {
+          LS[p] = (int)s[i];
+          LI[p] = inv;
+          if (mode == kSums && blockIdx.x == 0) {
+            if (a.s_l) a.s_l[(size_t)y * W + p] = (int)s[i];
+            if (a.s_ll) a.s_ll[(size_t)y * W + p] = (int)ss[i];
+          }
+        }
+      } else if (p < lay.nTS) {
+        TS[p] = (int)s[i];
+        TI[p] = inv;
+        if (mode == kSums) {
+          // each x' in [-(D-1), W-1] is written by exactly one chunk
+          const int xe = p - P - d0;
+          const bool own = (blockIdx.x == 0) ? (xe >= -P) : (xe <= -d0);
+          if (own && xe >= -(a.D - 1) && xe <= W - 1) {
+            const size_t idx = (size_t)y * (W + a.D - 1) + xe + a.D - 1;
+            if (a.s_t) a.s_t[idx] = (int)s[i];
+            if (a.s_tt) a.s_tt[idx] = (int)ss[i];
+          }
+        }
       }
     }
   }

@@ -230,12 +230,17 @@ __device__ __forceinline__ float carry_in(const float* B, const float* A, int se
 // ---------------------------------------------------------------------------
 // LDS layout of hpass_kernel, in 32-bit words (P = LPS - 1); every line array
 // below is followed by `pad` (= SEG) spare entries.
-//   LP[k][W+2R]   packed column bytes of the reference rows y-R..y+R: entry i is
-//                 column clamp(i-R); byte j of pack k is row y-R+4k+j (clamped),
-//                 zero past row y+R.
-//   LS, LI [W]    S_R(x) and 1/sqrt(l^2 S_RR - S_R^2) (0 for zero variance).
-//   TP[k][W+P+2R] packed target columns; entry i is column clamp(i-P-R-d0).
-//   TS, TI [W+P]  target window sum and inverse deviation at x' = t-P-d0.
+//   LR[W+2R][RS]  one record of RS = rec_words(R) words per entry i: the packed
+//                 column bytes of the reference rows y-R..y+R at column
+//                 clamp(i-R) (byte j of pack k is row y-R+4k+j, clamped, zero
+//                 past row y+R), then, for entries i < W, -S_R(i) and
+//                 1/sqrt(l^2 S_RR - S_R^2) (0 for zero variance) of position i.
+//   TR[W+P+2R][RS] target records: entry i packs column clamp(i-P-R-d0) and,
+//                 for i < W+P, holds S_T (not negated) and the inverse
+//                 deviation at x' = i-P-d0.
+//   A lane's cost at x0+k reads records at constant offsets from two per-lane
+//   bases; the odd stride keeps lanes that read consecutive records on distinct
+//   banks.
 //   WH[W+1]       W_L(x) for x in [0, W]; WH[0] = WH[W] = 0.
 //   EX, EX2 [16*64], EXS, EXS2 [kMaxSegs]   segment carries.
 //   GI, GO [W]    gains of the row before and after the pass pair (FP16
@@ -245,25 +250,24 @@ __device__ __forceinline__ float carry_in(const float* B, const float* A, int se
 //                 (FP16 H pairs over a stored volume only).
 // ---------------------------------------------------------------------------
 struct HLayout {
-  int nLP, nTP, nTS, oLP, oLS, oLI, oTP, oTS, oTI, oWH, oEX, oEXS, oEX2, oEXS2, oGI, oGO, oSI, words;
+  int nLP, nTP, nTS, oLP, oTP, oWH, oEX, oEXS, oEX2, oEXS2, oGI, oGO, oSI, words;
 };
+
+// Words per column record: the packs, the window sum and 1/sigma, rounded up to odd.
+__host__ __device__ constexpr int rec_words(int R) { return (packs_of(R) + 2) | 1; }
 
 __host__ __device__ constexpr HLayout h_layout(int W, int R, int LPS, int pad, bool zncc, bool dt, bool scaled) {
   HLayout L{};
-  const int NP = packs_of(R);
-  // packed columns: a row's W + 2R (reference) or nTS + 2R (target) columns,
-  // then padding (at least the kStatRun - 1 columns a statistics run reads past them)
-  L.nLP = W + 2 * R + (pad > 3 ? pad : 3);
+  const int RS = rec_words(R);
+  // records: a row's W + 2R (reference) or nTS + 2R (target) columns, then
+  // padding (at least the kStatRun - 1 columns a statistics run reads past them)
+  L.nLP = W + 2 * R + (pad > 4 ? pad : 4);
   L.nTS = W + LPS - 1;
-  L.nTP = L.nTS + 2 * R + (pad > 3 ? pad : 3);
+  L.nTP = L.nTS + 2 * R + (pad > 4 ? pad : 4);
   int o = 0;
   if (zncc) {
-    L.oLP = o; o += NP * L.nLP;
-    L.oLS = o; o += W + pad;
-    L.oLI = o; o += W + pad;
-    L.oTP = o; o += NP * L.nTP;
-    L.oTS = o; o += L.nTS + pad;
-    L.oTI = o; o += L.nTS + pad;
+    L.oLP = o; o += RS * L.nLP;
+    L.oTP = o; o += RS * L.nTP;
   }
   if (dt) {
     L.oWH = o; o += W + 1 + pad;
@@ -330,14 +334,17 @@ __device__ __forceinline__ float dt_weight(int ga, int gb, float inv_sigma_s, fl
 
 // Window sums of one image at kStatRun consecutive positions: the column sums
 // (of I and I^2, by dot4 over the packed rows) of the kStatRun + 2R columns
-// involved are formed once and the window slides over them.  P holds packed
-// columns pack-major with stride np; position p covers columns p .. p+2R.
-constexpr int kStatRun = 4;
-static_assert(kStatRun - 1 <= 3, "packed-column padding of h_layout");
+// involved are formed once and the window slides over them.  P holds column
+// records (packs first); position p covers records p .. p+2R.
+// Five positions per run: lanes then read records 5 * RS words apart, an odd
+// stride, so a wave's reads fall on distinct banks.
+constexpr int kStatRun = 5;
+static_assert(kStatRun - 1 <= 4, "record padding of h_layout");
 template <int R>
-__device__ __forceinline__ void window_run(const uint32_t* P, int np, int p0, uint32_t (&s)[kStatRun],
+__device__ __forceinline__ void window_run(const uint32_t* P, int p0, uint32_t (&s)[kStatRun],
                                            uint32_t (&ss)[kStatRun]) {
   constexpr int NP = packs_of(R);
+  constexpr int RS = rec_words(R);
   constexpr int NW = 2 * R + 1;
   constexpr int NC = kStatRun + 2 * R;
   uint32_t cs[NC], css[NC];
@@ -348,7 +355,7 @@ __device__ __forceinline__ void window_run(const uint32_t* P, int np, int p0, ui
     css[j] = 0;
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-      const uint32_t v = P[k * np + col];
+      const uint32_t v = P[col * RS + k];
       cs[j] = __builtin_amdgcn_udot4(v, 0x01010101u, cs[j], false);
       css[j] = __builtin_amdgcn_udot4(v, v, css[j], false);
     }
@@ -378,9 +385,10 @@ __device__ void stage_zncc(const HArgs& a, const HLayout& lay, uint32_t* smem, i
   constexpr int NW = 2 * R + 1;
   constexpr int N = NW * NW;
   constexpr int P = LPS - 1;
+  constexpr int RS = rec_words(R);
   const int tid = threadIdx.x, nt = blockDim.x, W = a.W, H = a.H;
-  uint32_t* LP = smem + lay.oLP;
-  uint32_t* TP = smem + lay.oTP;
+  uint32_t* LR = smem + lay.oLP;
+  uint32_t* TR = smem + lay.oTP;
   const uint8_t* lrow[NW];
   const uint8_t* trow[NW];
 #pragma unroll
@@ -399,7 +407,7 @@ __device__ void stage_zncc(const HArgs& a, const HLayout& lay, uint32_t* smem, i
 #pragma unroll
       for (int j = 0; j < 4; ++j)
         if (4 * k + j < NW) p |= (uint32_t)lrow[4 * k + j][col] << (8 * j);
-      LP[k * lay.nLP + i] = p;
+      LR[i * RS + k] = p;
     }
   }
   for (int i = tid; i < lay.nTS + 2 * R; i += nt) {
@@ -410,24 +418,22 @@ __device__ void stage_zncc(const HArgs& a, const HLayout& lay, uint32_t* smem, i
 #pragma unroll
       for (int j = 0; j < 4; ++j)
         if (4 * k + j < NW) p |= (uint32_t)trow[4 * k + j][col] << (8 * j);
-      TP[k * lay.nTP + i] = p;
+      TR[i * RS + k] = p;
     }
   }
   __syncthreads();
-  int32_t* LS = (int32_t*)(smem + lay.oLS);
-  float* LI = (float*)(smem + lay.oLI);
-  int32_t* TS = (int32_t*)(smem + lay.oTS);
-  float* TI = (float*)(smem + lay.oTI);
   // Runs of kStatRun positions: the first nrl threads take the reference
-  // positions x (columns x-R..x+R are LP entries x .. x+2R), the next nrt the
-  // target positions t, i.e. x' = t - P - d0 (TP entries t .. t+2R).
+  // positions x (columns x-R..x+R are LR entries x .. x+2R), the next nrt the
+  // target positions t, i.e. x' = t - P - d0 (TR entries t .. t+2R).  The
+  // statistics go to words NP, NP+1 of a position's own record, which no run
+  // reads.
   const int nrl = (W + kStatRun - 1) / kStatRun;
   const int nrt = (lay.nTS + kStatRun - 1) / kStatRun;
   for (int u = tid; u < nrl + nrt; u += nt) {
     const bool ref = u < nrl;
     const int p0 = (ref ? u : u - nrl) * kStatRun;
     uint32_t s[kStatRun], ss[kStatRun];
-    window_run<R>(ref ? LP : TP, ref ? lay.nLP : lay.nTP, p0, s, ss);
+    window_run<R>(ref ? LR : TR, p0, s, ss);
 #pragma unroll
     for (int i = 0; i < kStatRun; ++i) {
       const int p = p0 + i;
@@ -437,16 +443,16 @@ __device__ void stage_zncc(const HArgs& a, const HLayout& lay, uint32_t* smem, i
       const float inv = v > 0 ? __builtin_amdgcn_rsqf((float)v) : 0.0f;
       if (ref) {
         if (p < W) {
-          LS[p] = (int)s[i];
-          LI[p] = inv;
+          LR[p * RS + NP] = 0u - s[i];
+          LR[p * RS + NP + 1] = __float_as_uint(inv);
           if (mode == kSums && blockIdx.x == 0) {
             if (a.s_l) a.s_l[(size_t)y * W + p] = (int)s[i];
             if (a.s_ll) a.s_ll[(size_t)y * W + p] = (int)ss[i];
           }
         }
       } else if (p < lay.nTS) {
-        TS[p] = (int)s[i];
-        TI[p] = inv;
+        TR[p * RS + NP] = s[i];
+        TR[p * RS + NP + 1] = __float_as_uint(inv);
         if (mode == kSums) {
           // each x' in [-(D-1), W-1] is written by exactly one chunk
           const int xe = p - P - d0;
@@ -469,23 +475,31 @@ __device__ void stage_row_weights(const HArgs& a, float* WH, int y) {
     WH[x] = (x >= 1 && x < a.W) ? dt_weight(g[x], g[x - 1], a.inv_sigma_s, a.range_coef) : 0.0f;
 }
 
-// Cross-sum column at column p for this lane's disparity: sum_k dot4(L pack, T pack).
-template <int R, int LPS>
-__device__ __forceinline__ uint32_t colsum(const uint32_t* LP, const uint32_t* TP, int nLP, int nTP, int p,
-                                           int dloc) {
+// Cross-sum column of one window column for this lane's disparity, from the
+// column's reference and target records: sum_k dot4(L pack, T pack).
+template <int R>
+__device__ __forceinline__ uint32_t colsum(const uint32_t* lrec, const uint32_t* trec) {
   constexpr int NP = packs_of(R);
   uint32_t s = 0;
 #pragma unroll
-  for (int k = 0; k < NP; ++k)
-    s = __builtin_amdgcn_udot4(LP[k * nLP + p + R], TP[k * nTP + p + R + LPS - 1 - dloc], s, false);
+  for (int k = 0; k < NP; ++k) s = __builtin_amdgcn_udot4(lrec[k], trec[k], s, false);
   return s;
 }
 
-// cost = 1 - clamp(ZNCC, -1, 1) from the exact integer numerator l^2 S_RT - S_R S_T.
-// Both products stay below 2^32 for l <= 15 and the difference is below 2^31
-// in magnitude, so the wrapping 32-bit subtraction is exact.
-__device__ __forceinline__ float zncc_cost_from(uint32_t srt, int sl, float il, int st, float it, int N) {
-  const int num = (int)(__umul24((uint32_t)N, srt) - __umul24((uint32_t)sl, (uint32_t)st));
+// cost = 1 - clamp(ZNCC, -1, 1) from the exact integer numerator
+// l^2 S_RT - S_R S_T, given the records of the reference position and of the
+// target position (words NP, NP+1: -S_R and 1/sigma_R, S_T and 1/sigma_T).
+// l^2 S_RT and the window
+// sums stay below 2^24 for l <= 15 (24-bit multiplies), their product below
+// 2^32, and the numerator below 2^31 in magnitude, so the wrapping 32-bit sum
+// is exact.
+template <int R>
+__device__ __forceinline__ float zncc_cost_rec(uint32_t srt, const uint32_t* lrec, const uint32_t* trec) {
+  constexpr int NP = packs_of(R);
+  constexpr uint32_t N = (2 * R + 1) * (2 * R + 1);
+  const int nsl = (int)lrec[NP], st = (int)trec[NP];
+  const float il = __uint_as_float(lrec[NP + 1]), it = __uint_as_float(trec[NP + 1]);
+  const int num = (int)(__umul24(N, srt) + (uint32_t)__mul24(nsl, st));
   const float c = fmaf(-(float)num, il * it, 1.0f);
   return fminf(fmaxf(c, 0.0f), 2.0f);
 }
@@ -720,12 +734,16 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
   // uniform offset of step k, clamped into the segment
   auto step_soff = [&](int k) -> uint32_t { return (uint32_t)(kFull ? k : min(k, len - 1)) * xstride; };
 
-  const uint32_t* LP = smem + lay.oLP;
-  const uint32_t* TP = smem + lay.oTP;
-  const int32_t* LS = (const int32_t*)(smem + lay.oLS);
-  const float* LI = (const float*)(smem + lay.oLI);
-  const int32_t* TS = (const int32_t*)(smem + lay.oTS);
-  const float* TI = (const float*)(smem + lay.oTI);
+  // column records of position x0 (reference) and of its target at this
+  // lane's disparity; position x0+k and window column x0+k-R+i sit k and k+i
+  // records further on
+  constexpr int RS = rec_words(R);
+  uint32_t lo = lay.oLP + x0 * RS, to = lay.oTP + (x0 + LPS - 1 - dloc) * RS;
+  // opaque offsets: one base register each, every record read at a small
+  // constant offset from it (instead of rebasing each read pair)
+  asm volatile("" : "+v"(lo), "+v"(to));
+  const uint32_t* lrec = smem + lo;
+  const uint32_t* trec = smem + to;
 
   if constexpr (MODE == kSums || MODE == kCost) {
     static_assert(LPS == 64, "streaming modes use one segment per wave");
@@ -737,7 +755,7 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
     uint32_t S = 0;
 #pragma unroll
     for (int i = 0; i < NW; ++i) {
-      ring[i] = colsum<R, LPS>(LP, TP, lay.nLP, lay.nTP, x0 - R + i, dloc);
+      ring[i] = colsum<R>(lrec + i * RS, trec + i * RS);
       S += ring[i];
     }
     for (int kb = 0; kb < len; kb += NW) {
@@ -748,7 +766,7 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
           const int x = x0 + k;
           if (k > 0) {
             const int slot = (u + NW - 1) % NW;
-            const uint32_t cn = colsum<R, LPS>(LP, TP, lay.nLP, lay.nTP, x + R, dloc);
+            const uint32_t cn = colsum<R>(lrec + (k + 2 * R) * RS, trec + (k + 2 * R) * RS);
             S = S + cn - ring[slot];
             ring[slot] = cn;
           }
@@ -757,7 +775,7 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
             if constexpr (MODE == kSums) {
               a.s_rt[idx] = (int32_t)S;
             } else {
-              const float c = zncc_cost_from(S, LS[x], LI[x], TS[x + LPS - 1 - dloc], TI[x + LPS - 1 - dloc], N);
+              const float c = zncc_cost_rec<R>(S, lrec + k * RS, trec + k * RS);
               Elem<T>::store(vol + idx, c * a.out_scale);
             }
           }
@@ -784,7 +802,11 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
         }
       }
     }
-    const float* wp = WH + x0;  // W_L at x0 + k; padded past the row
+    // W_L at x0 + k (padded past the row), from an opaque base so that every
+    // step reads at a small constant offset
+    uint32_t wo = lay.oWH + x0;
+    asm volatile("" : "+v"(wo));
+    const float* wp = (const float*)(smem + wo);
     float c[SEG];
     // ---- loop A: values of the segment + carry-free L pass (ell) and weight product P
     float ell = 0.0f, P = 1.0f;
@@ -796,14 +818,14 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
       uint32_t S = 0;
 #pragma unroll
       for (int i = 0; i < NW; ++i) {
-        ring[i] = colsum<R, LPS>(LP, TP, lay.nLP, lay.nTP, x0 - R + i, dloc);
+        ring[i] = colsum<R>(lrec + i * RS, trec + i * RS);
         S += ring[i];
       }
 #pragma unroll
       for (int k = 0; k < SEG; ++k) {
         if (k > 0) {
           const int slot = (k - 1) % NW;
-          const uint32_t cn = colsum<R, LPS>(LP, TP, lay.nLP, lay.nTP, x0 + k + R, dloc);
+          const uint32_t cn = colsum<R>(lrec + (k + 2 * R) * RS, trec + (k + 2 * R) * RS);
           S = S + cn - ring[slot];
           ring[slot] = cn;
         }
@@ -818,8 +840,7 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
 #pragma unroll
       for (int k = 0; k < SEG; ++k) {
         const bool in = k < len;
-        const int x = x0 + k;
-        c[k] = zncc_cost_from(__float_as_uint(c[k]), LS[x], LI[x], TS[x + LPS - 1 - dloc], TI[x + LPS - 1 - dloc], N);
+        c[k] = zncc_cost_rec<R>(__float_as_uint(c[k]), lrec + k * RS, trec + k * RS);
         if constexpr (kInt) c[k] -= r0[k];
         const float w = wp[k];
         ell = in ? fmaf(w, ell, c[k]) : ell;
@@ -874,21 +895,24 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
     __syncthreads();
     const float kappa = carry_in<true>(EX2, EXS2, seg, a.nseg, LPS, dloc, max(a.nseg - 1 - wave * SPW, 0));
     reload_fence();
-    // ---- loop D: exact R pass from the true carry, then store
+    // ---- loop D: exact R pass from the true carry; each value is stored as
+    // soon as it is final, which spreads a workgroup's stores over the loop
     float next = kappa;
+    const float* so = GO + x0;  // output scale factors at x0 + k
+    // Lanes past the last disparity, and steps past a ragged segment, store
+    // at a lane offset beyond the row's buffer range, which the buffer unit
+    // discards (its range check covers the lane offset, not the step offset),
+    // so the stores need no branch.
+    constexpr uint32_t kDrop = 0x80000000u;
+    const uint32_t voff_st = active ? voff : kDrop;
 #pragma unroll
     for (int k = SEG - 1; k >= 0; --k) {
       const bool in = k < len;
       const float cr = fmaf(wp[k + 1], next, c[k]);
-      c[k] = in ? cr : c[k];
       next = in ? cr : next;
+      const float v = scaled ? cr * so[k] : cr * a.out_scale;
+      Elem<T>::bstore(vrs, in ? voff_st : kDrop, step_soff(k), v);
       step_fence(SEG - 1 - k, next);
-    }
-    const float* so = GO + x0;  // output scale factors at x0 + k
-#pragma unroll
-    for (int k = 0; k < SEG; ++k) {
-      const float v = scaled ? c[k] * so[k] : c[k] * a.out_scale;
-      if (k < len && active) Elem<T>::bstore(vrs, voff, step_soff(k), v);
     }
   }
 }

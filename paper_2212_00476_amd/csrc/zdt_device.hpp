@@ -671,7 +671,6 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
     a.ref0 = jb.ref0;
   }
   constexpr int NW = 2 * R + 1;  // window side
-  constexpr int N = NW * NW;
   constexpr int SPW = kWave / LPS;  // segments per wave
   constexpr bool kZncc = MODE != kHPair;
   constexpr bool kDT = MODE == kCostHPair || MODE == kHPair;
@@ -929,7 +928,7 @@ struct VArgs {
   const float* g_in;   // FP16 working volume: gain map [H][W] of the stored input
   float* g_out;        // and of the output (not for the WTA pass)
   int32_t* disp;       // WTA with a single chunk: final disparity
-  float* part_val;     // WTA with several chunks: [chunk][H][W] minimum
+  float* part_val;     // WTA with several chunks: [chunk][W][H] minimum (column-major)
   int32_t* part_idx;   // and its disparity
   int segl, nseg;      // segment length and number of segments of a column
   int nchunks;         // disparity chunks of LPS lanes
@@ -1321,8 +1320,10 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs args, VJobs jobs) {
         if (a.disp) {
           a.disp[p] = rd[r];
         } else {
-          a.part_val[(size_t)chunk * W * H + p] = kInt ? key_value(rv[r]) : __uint_as_float(rv[r]);
-          a.part_idx[(size_t)chunk * W * H + p] = rd[r];
+          // column-major partials: the wave's rows are consecutive words
+          const size_t q = (size_t)chunk * W * H + (size_t)x * H + (y0 + k);
+          a.part_val[q] = kInt ? key_value(rv[r]) : __uint_as_float(rv[r]);
+          a.part_idx[q] = rd[r];
         }
       }
     }
@@ -1338,20 +1339,41 @@ struct WJob {
 struct WJobs {
   WJob j[kMaxJobs];
 };
-[[maybe_unused]] static __global__ void wta_combine_kernel(WJobs jobs, int nchunks, int npix) {
+// The partial minima are stored column-major ([chunk][x][y]: a V-pass wave's
+// pixels are consecutive rows of one column); a 32 x 32 tile is combined with
+// reads along y, transposed through LDS and written along x.  Block 32 x 8.
+constexpr int kCombineTile = 32;
+[[maybe_unused]] static __global__ void wta_combine_kernel(WJobs jobs, int nchunks, int W, int H) {
+  __shared__ int32_t tile[kCombineTile][kCombineTile + 1];
   const WJob& jb = jobs.j[blockIdx.z];
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= npix) return;
-  float best = jb.part_val[p];
-  int idx = jb.part_idx[p];
-  for (int c = 1; c < nchunks; ++c) {
-    const float v = jb.part_val[(size_t)c * npix + p];
-    if (v < best) {
-      best = v;
-      idx = jb.part_idx[(size_t)c * npix + p];
+  const int tx = threadIdx.x % kCombineTile, ty = threadIdx.x / kCombineTile;
+  const int x0 = blockIdx.x * kCombineTile, y0 = blockIdx.y * kCombineTile;
+  const size_t npix = (size_t)W * H;
+#pragma unroll
+  for (int j = ty; j < kCombineTile; j += 8) {
+    const int x = x0 + j, y = y0 + tx;
+    if (x < W && y < H) {
+      // every chunk's minimum and disparity are loaded unconditionally, so all
+      // the loads are in flight at once (no load waits on a comparison)
+      const size_t q = (size_t)x * H + y;
+      float best = jb.part_val[q];
+      int idx = jb.part_idx[q];
+#pragma unroll 4
+      for (int c = 1; c < nchunks; ++c) {
+        const float v = jb.part_val[c * npix + q];
+        const int i = jb.part_idx[c * npix + q];
+        idx = v < best ? i : idx;  // strict: the lower chunk (lower d) keeps a tie
+        best = fminf(v, best);
+      }
+      tile[j][tx] = idx;
     }
   }
-  jb.disp[p] = idx;
+  __syncthreads();
+#pragma unroll
+  for (int j = ty; j < kCombineTile; j += 8) {
+    const int y = y0 + j, x = x0 + tx;
+    if (x < W && y < H) jb.disp[(size_t)y * W + x] = tile[tx][j];
+  }
 }
 
 // Test entry of the 8-bit code: codes[i] = encode(in[i]), decoded[i] = decode(codes[i]).

@@ -429,7 +429,6 @@ int solve_group(const zdt_params* p, const JobPtrs* jobs, int n, hipStream_t s) 
   const bool ints = int_vol(p->vol_dtype);       // T-scaled, centred integer volume
   const int vchunks = wta_chunks(p, pl.v_lanes);
   const bool multi = vchunks > 1;
-  const size_t npix = (size_t)p->width * p->height;
   HJobs ht{};
   VJobs vt{};
   WJobs wt{};
@@ -473,9 +472,10 @@ int solve_group(const zdt_params* p, const JobPtrs* jobs, int n, hipStream_t s) 
     rc = launch_v(p, scaled, it + 1 == p->dt_iters, va, vt, n, pl, s);
   }
   if (rc == ZDT_OK && multi) {
-    const int threads = 256;
-    rc = launch("wta_combine", wta_combine_kernel, dim3((unsigned)((npix + threads - 1) / threads), 1, n),
-                dim3(threads), 0, s, wt, vchunks, (int)npix);
+    const dim3 grid((unsigned)((p->width + kCombineTile - 1) / kCombineTile),
+                    (unsigned)((p->height + kCombineTile - 1) / kCombineTile), n);
+    rc = launch("wta_combine", wta_combine_kernel, grid, dim3(kCombineTile * 8), 0, s, wt, vchunks, p->width,
+                p->height);
   }
   return rc;
 }

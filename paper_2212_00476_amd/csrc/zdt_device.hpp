@@ -1339,6 +1339,111 @@ struct WJob {
 struct WJobs {
   WJob j[kMaxJobs];
 };
+// The raw cost at d = 0 of every pixel: the centring reference of the integer
+// volumes (Eq. DT_new with d_arb = 0).  The arithmetic is that of the fused
+// cost pass, so the centred d = 0 slice comes out exactly zero.  One workgroup
+// per row packs both images' window columns (the target column at d = 0 is the
+// reference column), then each thread forms the five window sums S_R, S_RR,
+// S_T, S_TT and S_RT of kStatRun consecutive positions from column sums.
+struct Ref0Job {
+  const uint8_t* left;
+  const uint8_t* right;
+  float* ref0;  // [H][W]
+};
+struct Ref0Jobs {
+  Ref0Job j[kMaxJobs];
+};
+constexpr int kRef0Threads = 256;
+__host__ __device__ constexpr int ref0_cols(int W, int R) { return W + 2 * R + kStatRun - 1; }
+__host__ __device__ constexpr int ref0_lds_words(int W, int R) { return 2 * packs_of(R) * ref0_cols(W, R); }
+
+template <int R>
+__global__ __launch_bounds__(kRef0Threads) void zncc_ref0_kernel(Ref0Jobs jobs, int pitch, int W, int H) {
+  extern __shared__ uint32_t smem[];
+  constexpr int NP = packs_of(R);
+  constexpr int NW = 2 * R + 1;
+  constexpr uint32_t N = NW * NW;
+  constexpr int NC = kStatRun + 2 * R;
+  const Ref0Job& jb = jobs.j[blockIdx.z];
+  const int y = blockIdx.x;
+  const int ncol = ref0_cols(W, R);
+  uint32_t* LPK = smem;              // [ncol][NP] packed reference columns
+  uint32_t* TPK = smem + ncol * NP;  // and target columns
+  const uint8_t* lrow[NW];
+  const uint8_t* trow[NW];
+#pragma unroll
+  for (int q = 0; q < NW; ++q) {
+    const size_t off = (size_t)clampi(y - R + q, 0, H - 1) * pitch;
+    lrow[q] = jb.left + off;
+    trow[q] = jb.right + off;
+  }
+  for (int i = threadIdx.x; i < ncol; i += blockDim.x) {
+    const int col = clampi(i - R, 0, W - 1);
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      uint32_t pl = 0, pt = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (4 * k + j < NW) {
+          pl |= (uint32_t)lrow[4 * k + j][col] << (8 * j);
+          pt |= (uint32_t)trow[4 * k + j][col] << (8 * j);
+        }
+      LPK[i * NP + k] = pl;
+      TPK[i * NP + k] = pt;
+    }
+  }
+  __syncthreads();
+  const int nr = (W + kStatRun - 1) / kStatRun;
+  for (int u = threadIdx.x; u < nr; u += blockDim.x) {
+    const int p0 = u * kStatRun;
+    // column sums of I_R, I_R^2, I_T, I_T^2 and I_R I_T over the window rows
+    uint32_t cl[NC], cll[NC], ct[NC], ctt[NC], clt[NC];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      cl[j] = cll[j] = ct[j] = ctt[j] = clt[j] = 0;
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        const uint32_t l = LPK[(p0 + j) * NP + k], t = TPK[(p0 + j) * NP + k];
+        cl[j] = __builtin_amdgcn_udot4(l, 0x01010101u, cl[j], false);
+        cll[j] = __builtin_amdgcn_udot4(l, l, cll[j], false);
+        ct[j] = __builtin_amdgcn_udot4(t, 0x01010101u, ct[j], false);
+        ctt[j] = __builtin_amdgcn_udot4(t, t, ctt[j], false);
+        clt[j] = __builtin_amdgcn_udot4(l, t, clt[j], false);
+      }
+    }
+    uint32_t sl = 0, sll = 0, st = 0, stt = 0, slt = 0;
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+      sl += cl[j];
+      sll += cll[j];
+      st += ct[j];
+      stt += ctt[j];
+      slt += clt[j];
+    }
+#pragma unroll
+    for (int i = 0; i < kStatRun; ++i) {
+      if (i > 0) {
+        sl += cl[i + 2 * R] - cl[i - 1];
+        sll += cll[i + 2 * R] - cll[i - 1];
+        st += ct[i + 2 * R] - ct[i - 1];
+        stt += ctt[i + 2 * R] - ctt[i - 1];
+        slt += clt[i + 2 * R] - clt[i - 1];
+      }
+      const int p = p0 + i;
+      if (p < W) {
+        // as stage_zncc and zncc_cost_rec
+        const int vl = (int)(__umul24(N, sll) - __umul24(sl, sl));
+        const int vt = (int)(__umul24(N, stt) - __umul24(st, st));
+        const float il = vl > 0 ? __builtin_amdgcn_rsqf((float)vl) : 0.0f;
+        const float it = vt > 0 ? __builtin_amdgcn_rsqf((float)vt) : 0.0f;
+        const int num = (int)(__umul24(N, slt) + (uint32_t)__mul24(-(int)sl, (int)st));
+        const float c = fmaf(-(float)num, il * it, 1.0f);
+        jb.ref0[(size_t)y * W + p] = fminf(fmaxf(c, 0.0f), 2.0f);
+      }
+    }
+  }
+}
+
 // The partial minima are stored column-major ([chunk][x][y]: a V-pass wave's
 // pixels are consecutive rows of one column); a 32 x 32 tile is combined with
 // reads along y, transposed through LDS and written along x.  Block 32 x 8.

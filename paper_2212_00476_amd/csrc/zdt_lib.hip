@@ -349,6 +349,26 @@ int launch_h(const zdt_params* p, int dtype, int mode, bool scaled, HArgs a, con
   return fail(ZDT_EINVAL, "bad dtype %d", dtype);
 }
 
+// The d = 0 raw cost of n pairs (integer volumes' centring reference).
+template <int R>
+int launch_ref0_r(const zdt_params* p, const Ref0Jobs& t, int n, hipStream_t s) {
+  return launch("zncc_ref0", zncc_ref0_kernel<R>, dim3(p->height, 1, n), dim3(kRef0Threads),
+                (size_t)ref0_lds_words(p->width, R) * 4, s, t, p->pitch, p->width, p->height);
+}
+int launch_ref0(const zdt_params* p, const Ref0Jobs& t, int n, hipStream_t s) {
+  switch (p->radius) {
+    case 0: return launch_ref0_r<0>(p, t, n, s);
+    case 1: return launch_ref0_r<1>(p, t, n, s);
+    case 2: return launch_ref0_r<2>(p, t, n, s);
+    case 3: return launch_ref0_r<3>(p, t, n, s);
+    case 4: return launch_ref0_r<4>(p, t, n, s);
+    case 5: return launch_ref0_r<5>(p, t, n, s);
+    case 6: return launch_ref0_r<6>(p, t, n, s);
+    case 7: return launch_ref0_r<7>(p, t, n, s);
+  }
+  return fail(ZDT_EUNSUPPORTED, "zncc_ref0: radius %d", p->radius);
+}
+
 int launch_v(const zdt_params* p, bool scaled, bool wta, VArgs a, const VJobs& t, int n, const Plan& pl,
              hipStream_t s) {
   const Split sp = v_split_plan(p->height, pl);
@@ -456,13 +476,9 @@ int solve_group(const zdt_params* p, const JobPtrs* jobs, int n, hipStream_t s) 
     // centring reference (Eq. DT_new with d_arb = 0): the raw cost slice d = 0,
     // subtracted from every raw cost before the first pass.  The passes are
     // linear and map the zero slice to zero, so every later stage stays centred.
-    zdt_params p0 = *p;
-    p0.max_disp = 1;
-    p0.vol_dtype = ZDT_F32;
-    HJobs rt{};
-    for (int i = 0; i < n; ++i)
-      rt.j[i] = {jobs[i].left, jobs[i].right, nullptr, (void*)ht.j[i].ref0, nullptr, nullptr, nullptr};
-    rc = launch_h(&p0, ZDT_F32, kCost, false, make_hargs(&p0, 1.0f), rt, n, pl, s);
+    Ref0Jobs rt{};
+    for (int i = 0; i < n; ++i) rt.j[i] = {jobs[i].left, jobs[i].right, const_cast<float*>(ht.j[i].ref0)};
+    rc = launch_ref0(p, rt, n, s);
   }
   // sweep 1: cost fused with L, R; then U, D.  Sweeps 2..I: L, R; U, D.  The
   // last U, D pair carries the WTA and writes no volume.

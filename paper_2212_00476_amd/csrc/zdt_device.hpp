@@ -489,10 +489,9 @@ __device__ __forceinline__ uint32_t colsum(const uint32_t* lrec, const uint32_t*
 // cost = 1 - clamp(ZNCC, -1, 1) from the exact integer numerator
 // l^2 S_RT - S_R S_T, given the records of the reference position and of the
 // target position (words NP, NP+1: -S_R and 1/sigma_R, S_T and 1/sigma_T).
-// l^2 S_RT and the window
-// sums stay below 2^24 for l <= 15 (24-bit multiplies), their product below
-// 2^32, and the numerator below 2^31 in magnitude, so the wrapping 32-bit sum
-// is exact.
+// For l <= 15, S_RT and the window sums are below 2^24 (exact operands of the
+// 24-bit multiplies), the products l^2 S_RT and S_R S_T below 2^32, and the
+// numerator below 2^31 in magnitude, so the wrapping 32-bit sum is exact.
 template <int R>
 __device__ __forceinline__ float zncc_cost_rec(uint32_t srt, const uint32_t* lrec, const uint32_t* trec) {
   constexpr int NP = packs_of(R);

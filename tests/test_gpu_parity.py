@@ -479,18 +479,25 @@ def test_i8_codec_on_device_matches_oracle():
 
 
 @pytest.mark.parametrize("dtype", [zdt.ZDT_I16, zdt.ZDT_I8], ids=["i16", "i8"])
-def test_integer_volume_centred_slice_is_zero(dtype):
+@pytest.mark.parametrize("W,r", [(160, 2), (157, 0), (133, 4), (101, 5), (96, 6), (77, 7)])
+def test_integer_volume_centred_slice_is_zero(dtype, W, r):
     """The d_arb = 0 slice is subtracted before the first pass; the passes map
-    a zero slice to zero, so every stored state has an all-zero slice d = 0."""
-    W, H, D, r = 160, 60, 40, 2
-    pr = pair_for(W, H, D, seed=13)
+    a zero slice to zero, so every stored state has an all-zero slice d = 0.
+    The reference slice comes from its own kernel, so this also checks that it
+    equals the fused pass's d = 0 cost bit for bit, at every radius (widths not
+    a multiple of the five-position runs of either kernel)."""
+    H, D = 60, 40
+    pr = pair_for(W, H, D, seed=13 + r)
     p = zdt.params(W, H, D, r, 5.0, 52.0 / 255.0, 2, vol_dtype=dtype)
     s = zdt.Solver(p)
     disp = s(dev(pr.left), dev(pr.right))
     torch.cuda.synchronize()
     vol = s.vol.cpu().numpy()           # holds the second H pair's output
     assert np.all(vol[:, :, 0] == 0)
-    assert np.any(vol[:, :, 1:] != 0)
+    if r > 0:  # a 1x1 window has no variance: every cost is 1, the centred volume 0
+        assert np.any(vol[:, :, 1:] != 0)
+    else:
+        assert np.all(vol == 0)
     d = disp.cpu().numpy()
     assert d.min() >= 0 and d.max() < D
 

@@ -300,6 +300,27 @@ def test_stereo_solve_narrow_several_chunks(shape, dtype):
     assert mism <= (5e-3 if dtype == zdt.ZDT_F16 else 3e-2)
 
 
+@pytest.mark.parametrize("dtype", [zdt.ZDT_F32, zdt.ZDT_F16], ids=["f32", "f16"])
+def test_widest_row_largest_window(dtype):
+    """The largest LDS layout of the fused cost pass: a 1920-wide row (32
+    segments of 60) with the 15x15 window, whose column records are 7 words
+    (about 145 KB of LDS with the FP16 gain lines).  Disparities against the
+    FP64 oracle, with the bars of the other end-to-end tests."""
+    W, H, D, r = 1920, 24, 64, 7
+    note(f"stereo_solve {W}x{H} D={D} r={r} dtype={dtype}")
+    pr = pair_for(W, H, D, seed=21)
+    disp = _solve_gpu(pr, D, r, dtype)
+    o_disp, cagg = oracle.stereo_solve(pr.left, pr.right, D, r, 20.0, 0.1, 3, keep_volume=True)
+    slack, ok = _near_tie_ok(disp, cagg)
+    mism = (disp != o_disp).mean()
+    note(f"  mismatch {100 * mism:.4f} %")
+    if dtype == zdt.ZDT_F32:
+        assert ok.all(), slack[~ok].max()
+    else:
+        rel = (slack / np.maximum(np.abs(cagg).max(axis=2), 1e-300)).max()
+        assert rel <= 5e-3 and mism <= 5e-3, (rel, mism)
+
+
 def test_fused_equals_unfused_fp32():
     """stereo_solve (cost fused into the first H pair, WTA into the last V
     pair) equals zncc_cost_volume + dt_aggregate + wta_disparity bit for bit."""
@@ -479,7 +500,7 @@ def test_i8_codec_on_device_matches_oracle():
 
 
 @pytest.mark.parametrize("dtype", [zdt.ZDT_I16, zdt.ZDT_I8], ids=["i16", "i8"])
-@pytest.mark.parametrize("W,r", [(160, 2), (157, 0), (133, 4), (101, 5), (96, 6), (77, 7)])
+@pytest.mark.parametrize("W,r", [(160, 2), (157, 0), (133, 4), (101, 5), (96, 6), (77, 7), (1920, 7)])
 def test_integer_volume_centred_slice_is_zero(dtype, W, r):
     """The d_arb = 0 slice is subtracted before the first pass; the passes map
     a zero slice to zero, so every stored state has an all-zero slice d = 0.

@@ -151,9 +151,15 @@ __device__ __forceinline__ int wave_argmin(const float (&v)[DPL], int lane) {
 }
 
 // Pixel ring depth: K pixels of cost (and of stored sums) in flight per wave.
-template <int DPL>
+// With 16-bit costs a pixel's loads are fewer bytes, and the row pass (one
+// wave per path of a row, fewer waves than SIMDs) is bound by the loads in
+// flight: twice the depth took its time from 246 to 226 us at 1280x384,
+// D = 128, while the FP32-cost passes, already at the memory's rate, gained
+// nothing from it.
+template <int DPL, typename E>
 constexpr int ring_depth() {
-  return DPL == 1 ? 16 : (DPL == 2 ? 12 : 8);
+  constexpr int k = DPL == 1 ? 16 : (DPL == 2 ? 12 : 8);
+  return sizeof(E) == 2 ? 2 * k : k;
 }
 
 // Run `count` pixels of one path, starting at pixel p0 and stepping by dp.
@@ -162,7 +168,7 @@ constexpr int ring_depth() {
 template <typename E, int DPL, bool VEC, bool PAD, bool LOADS, bool STORES, bool WTA>
 __device__ __forceinline__ void sgm_run(const SgmArgs& a, int p0, int dp, int count, float (&L)[DPL], float& m,
                                         const float (&pad)[DPL], int lane) {
-  constexpr int K = ring_depth<DPL>();
+  constexpr int K = ring_depth<DPL, E>();
   if (count <= 0) return;
   const int D = a.D;
   const E* cost = static_cast<const E*>(a.cost);

@@ -1,0 +1,58 @@
+"""Time ``stereo_solve`` on one of the named synthetic workloads.
+
+    python -m paper_2212_00476_amd.timing planes_1920x1080_d256 --dtype f32 --dtype f16 --steps 10
+
+Prints one line per volume type: milliseconds per pair (wall clock over
+`steps` solves after `warmup` untimed ones, default plan, 9x9 window, three
+sweeps) and each kernel's average time from HIP events that the library
+records on its launch stream.  Inputs stay resident on the device; nothing
+is checked (the tests do that).  Also serves as the program to run under
+rocprofv3 for a per-kernel summary of a workload.
+"""
+from __future__ import annotations
+
+import argparse
+import time
+
+DTYPES = ("f32", "f16", "bf16", "i16", "i8")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("workload", help="planes_1280x384_d128, planes_1920x1080_d256, planes_640x192_d64, ...")
+    ap.add_argument("--dtype", action="append", choices=DTYPES, help="volume type (repeatable; default f32)")
+    ap.add_argument("--radius", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    args = ap.parse_args(argv)
+
+    import torch
+
+    from . import ZDT_BF16, ZDT_F16, ZDT_F32, ZDT_I8, ZDT_I16, Solver, params, profile_collect, profile_enable
+    from . import scenes
+
+    codes = {"f32": ZDT_F32, "f16": ZDT_F16, "bf16": ZDT_BF16, "i16": ZDT_I16, "i8": ZDT_I8}
+    pr = scenes.workload(args.workload)
+    H, W = pr.left.shape
+    D = int(args.workload.rsplit("_d", 1)[1])
+    left, right = torch.from_numpy(pr.left).cuda(), torch.from_numpy(pr.right).cuda()
+    for name in args.dtype or ["f32"]:
+        solver = Solver(params(W, H, D, args.radius, vol_dtype=codes[name]))
+        for _ in range(args.warmup):
+            solver(left, right)
+        torch.cuda.synchronize()
+        profile_enable(True)
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            solver(left, right)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) / args.steps * 1e3
+        profile_enable(False)
+        kernels = {k: round(1e3 * v / n, 1) for k, (v, n) in profile_collect().items()}
+        print(f"{args.workload} {name}: {ms:.3f} ms per pair; kernel avg us {kernels}", flush=True)
+        del solver
+        torch.cuda.empty_cache()
+
+
+if __name__ == "__main__":
+    main()

@@ -16,6 +16,7 @@ from __future__ import annotations
 import ctypes
 import os
 import subprocess
+from collections import namedtuple
 
 import numpy as np
 
@@ -58,7 +59,9 @@ def _load():
         lib.oracle_wta.argtypes = [P, I, I, I, P]
         lib.oracle_stereo_solve.argtypes = [P, P, I, I, I, I, I, Dbl, Dbl, I, I, P, P]
         lib.oracle_sgm_aggregate.argtypes = [P, I, I, I, Dbl, Dbl, Dbl, P]
-        lib.oracle_int_solve.argtypes = [P, P, I, I, I, I, I, Dbl, Dbl, I, I, Dbl, I, P, P]
+        lib.oracle_int_solve.argtypes = [P, P, I, I, I, I, I, Dbl, Dbl, I, I, Dbl, I, I, I, P, P, P]
+        lib.oracle_dt_passes.argtypes = [P, I, I, P, P, I, I]
+        lib.oracle_dt_passes.restype = ctypes.c_int
         lib.oracle_int_solve.restype = ctypes.c_int
         lib.oracle_sgm_aggregate.restype = ctypes.c_int
         lib.oracle_i8_encode.argtypes = [ctypes.c_int16]
@@ -194,19 +197,44 @@ def stereo_solve(left, right, D, r, sigma_s, sigma_r, iters, guide_target=False,
     return (disp, vol) if keep_volume else disp
 
 
-def int_solve(left, right, D, r, sigma_s, sigma_r, iters, T=21.0, code8=False, guide_target=False,
-              keep_volume=False):
-    """The integer-volume path (Sec. IV-C): centred cost, DT pass pairs with the
-    stored state quantized to int16 (or its 8-bit code) between pairs, WTA.
-    Returns disp [H][W] int32, and the last pair's output if asked."""
+IntSolve = namedtuple("IntSolve", "disp volume saturated")
+
+
+def int_solve(left, right, D, r, sigma_s, sigma_r, iters, T=21.0, code8=False, form="paper", guide_target=False,
+              keep_volume=False, npasses=0):
+    """The integer-volume path (Sec. IV-C): T-scaled int16 states (or their
+    8-bit code), normalized by Eq. DT_new with d_arb = 0, DT, WTA.
+
+    form "paper": the per-pass FastDT of Sec. V-C (a stored state after every
+    pass but the last; Int16 normalizes in U2D, Int8 in R2L and codes R2L's
+    output).  form "pairs": centred once before the first pass, states stored
+    only between pass pairs.  Returns IntSolve(disp [H][W] int32, the last
+    pass's output [H][W][D] float64 if asked else None, number of stores that
+    saturated).  npasses in 1 .. 4 iters stops after that many passes of the
+    sequence L, R, U, D, ... (0: all); the state returned is then the stored
+    one if the stop is a store point (the WTA runs on it)."""
     L, R = _u8(left), _u8(right)
     H, W = L.shape
     disp = np.empty((H, W), np.int32)
     vol = np.empty((H, W, D), np.float64) if keep_volume else None
+    sat = ctypes.c_int64(0)
+    f = {"paper": 0, "pairs": 1}[form]
     _check(_load().oracle_int_solve(_ptr(L), _ptr(R), W, W, H, D, r, float(sigma_s), float(sigma_r), int(iters),
-                                    int(bool(guide_target)), float(T), int(bool(code8)),
-                                    _ptr(vol) if vol is not None else None, _ptr(disp)), "int_solve")
-    return (disp, vol) if keep_volume else disp
+                                    int(bool(guide_target)), float(T), int(bool(code8)), f, int(npasses),
+                                    _ptr(vol) if vol is not None else None, _ptr(disp), ctypes.byref(sat)),
+           "int_solve")
+    return IntSolve(disp, vol, int(sat.value))
+
+
+def dt_passes(c_hw, wh, wv, first, count):
+    """Passes first .. first+count-1 of the sequence L, R, U, D, L, ... on one
+    [H][W] slice (returns a new array)."""
+    c = np.array(c_hw, dtype=np.float64, order="C", copy=True)
+    H, W = c.shape
+    wh = np.ascontiguousarray(wh, np.float64)
+    wv = np.ascontiguousarray(wv, np.float64)
+    _check(_load().oracle_dt_passes(_ptr(c), W, H, _ptr(wh), _ptr(wv), int(first), int(count)), "dt_passes")
+    return c
 
 
 def solve_slices(left, right, r, ds, sigma_s, sigma_r, iters, guide_target=False, threads=1):

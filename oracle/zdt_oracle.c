@@ -299,67 +299,163 @@ int16_t oracle_i8_decode(uint8_t c) {
 }
 
 /* ---------------------------------------------------------------------------
- * The paper's narrow integer volumes (Sec. IV-C) as a whole path.  The cost
- * 1 - ZNCC is made nearly zero-mean by subtracting its slice at d_arb = 0
- * (Eq. DT_new; the recursions are linear and map a zero slice to zero, so the
- * subtraction is done once, before the first pass).  The DT then runs as pass
- * pairs, L then R along rows and U then D along columns, and the state stored
- * between two pairs is quantized: v becomes q = sat16(round(T v)), rounding
- * halves to even; with code8 the stored byte is q's 8-bit code, so q becomes
- * decode(encode(q)); the next pair reads q / T.  The last pair's output is not
- * stored: it goes to the WTA as is.  Only iters >= 1 is defined.
- * final_hwd (nullable) receives that last output.
+ * Single DT passes on one contiguous slice [H][W] (Eqs. DT1-DT4 one at a
+ * time), and a run of them: passes first .. first+count-1 of the sequence
+ * L, R, U, D, L, R, U, D, ... (pass k is L, R, U, D for k mod 4 = 0 .. 3).
+ * count = 4*I from first = 0 is I sweeps, the same as oracle_dt_slice.
  * ------------------------------------------------------------------------- */
-static double quantize16(double v, double T, int code8) {
+static void pass_l(double* c, int W, int H, const double* wh) {
+  for (int y = 0; y < H; ++y)
+    for (int x = 1; x < W; ++x) c[(ptrdiff_t)y * W + x] += wh[(ptrdiff_t)y * W + x] * c[(ptrdiff_t)y * W + x - 1];
+}
+static void pass_r(double* c, int W, int H, const double* wh) {
+  for (int y = 0; y < H; ++y)
+    for (int x = W - 2; x >= 0; --x)
+      c[(ptrdiff_t)y * W + x] += wh[(ptrdiff_t)y * W + x + 1] * c[(ptrdiff_t)y * W + x + 1];
+}
+static void pass_u(double* c, int W, int H, const double* wv) {
+  for (int x = 0; x < W; ++x)
+    for (int y = 1; y < H; ++y) c[(ptrdiff_t)y * W + x] += wv[(ptrdiff_t)y * W + x] * c[(ptrdiff_t)(y - 1) * W + x];
+}
+static void pass_d(double* c, int W, int H, const double* wv) {
+  for (int x = 0; x < W; ++x)
+    for (int y = H - 2; y >= 0; --y)
+      c[(ptrdiff_t)y * W + x] += wv[(ptrdiff_t)(y + 1) * W + x] * c[(ptrdiff_t)(y + 1) * W + x];
+}
+static void pass_k(double* c, int W, int H, const double* wh, const double* wv, int k) {
+  switch (k & 3) {
+    case 0: pass_l(c, W, H, wh); break;
+    case 1: pass_r(c, W, H, wh); break;
+    case 2: pass_u(c, W, H, wv); break;
+    default: pass_d(c, W, H, wv); break;
+  }
+}
+
+int oracle_dt_passes(double* c_hw, int W, int H, const double* wh, const double* wv, int first, int count) {
+  if (W < 1 || H < 1 || first < 0 || count < 0) return -1;
+  for (int k = first; k < first + count; ++k) pass_k(c_hw, W, H, wh, wv, k);
+  return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * The paper's narrow integer volumes (Sec. IV-C) as a whole path, in two
+ * forms.  Common to both: a stored state v is kept as q = sat16(round(T v)),
+ * rounding halves to even (T is the integer coefficient of Sec. IV-C, 21 in
+ * Sec. V-C); a state stored as an 8-bit code keeps decode(encode(q)); a
+ * stored state is read back as q / T.  The normalization of Eq. DT_new
+ * subtracts, inside a pass, the pass input's value at d_arb = 0 at the same
+ * pixel before the recursion, so the pass output's d_arb slice is zero.  The
+ * DT's last pass is not stored: its output goes to the WTA as is.  Sweeps
+ * after the first repeat the four passes (iters >= 1 only).
+ *
+ * form ORACLE_INT_PAPER -- the FastDT of Sec. V-C and Table II, one kernel per
+ *   pass, so the volume is stored after every pass but the last (after L2R,
+ *   R2L, U2D, and after D2U of every sweep but the last):
+ *     Int16 (code8 = 0): every stored state is int16; the normalization runs
+ *       in the U2D pass.
+ *     Int8 (code8 = 1): the normalization runs in the R2L pass, whose output
+ *       is stored as the 8-bit code ("encoding at the end of R2L"); U2D reads
+ *       the decoded value ("decoding at the beginning of U2D"); the L2R and
+ *       U2D outputs are int16.  Sweeps after the first are not in the paper;
+ *       the D2U output that the next sweep reads is stored like R2L's, as the
+ *       8-bit code.
+ *   In later sweeps the d_arb slice entering the normalization is already
+ *   zero, so subtracting it changes nothing; it is still done, as stated.
+ * form ORACLE_INT_PAIRS -- the state crosses memory only between pass pairs:
+ *   the raw cost is centred once, before the first pass (subtracting its
+ *   d_arb = 0 slice; the passes are linear and keep a zero slice zero), and
+ *   the output of every L,R pair and of every U,D pair but the last is
+ *   stored, as int16 or (code8) as the 8-bit code.
+ *
+ * npasses in 1 .. 4*iters stops after that many passes (0: all of them); the
+ * state returned is then the stored one when the stop is a store point.
+ * final_hwd (nullable) receives that state; *saturated (nullable) counts the
+ * stores whose rounded value fell outside the int16 range.  The WTA runs on
+ * the returned state.
+ * ------------------------------------------------------------------------- */
+enum { ORACLE_INT_PAPER = 0, ORACLE_INT_PAIRS = 1 };
+
+static double store_state(double v, double T, int code8, int64_t* sat) {
   double q = nearbyint(T * v); /* default rounding mode: to nearest, ties to even */
-  if (q > 32767.0) q = 32767.0;
-  if (q < -32768.0) q = -32768.0;
+  if (q > 32767.0 || q < -32768.0) {
+    ++*sat;
+    q = q > 0.0 ? 32767.0 : -32768.0;
+  }
   int16_t s = (int16_t)q;
   if (code8) s = oracle_i8_decode(oracle_i8_encode(s));
   return (double)s / T;
 }
 
-static void h_pair(double* c, int W, int H, const double* wh) {
-  for (int y = 0; y < H; ++y) {
-    double* row = c + (ptrdiff_t)y * W;
-    const double* w = wh + (ptrdiff_t)y * W;
-    for (int x = 1; x < W; ++x) row[x] += w[x] * row[x - 1];
-    for (int x = W - 2; x >= 0; --x) row[x] += w[x + 1] * row[x + 1];
+static void store_slice(double* c, size_t np, double T, int code8, int64_t* sat) {
+  for (size_t p = 0; p < np; ++p) c[p] = store_state(c[p], T, code8, sat);
+}
+
+/* Eq. DT_new's subtraction: the pass input minus the input's d_arb slice.
+ * With ref == NULL the slice being processed is the d_arb slice itself; its
+ * input is first recorded into rec (if not NULL). */
+static void normalize_slice(double* c, size_t np, const double* ref, double* rec) {
+  if (rec) memcpy(rec, c, np * sizeof(double));
+  for (size_t p = 0; p < np; ++p) c[p] -= ref ? ref[p] : c[p];
+}
+
+/* One disparity slice through the paper's per-pass form, npasses passes.
+ * refs[it] is the d_arb slice's input to the normalizing pass of sweep it:
+ * read when `record` is 0, written when it is 1 (the d_arb slice itself). */
+static void int_slice_paper(double* c, int W, int H, const double* wh, const double* wv, int iters, int npasses,
+                            double T, int code8, double* const* refs, int record, int64_t* sat) {
+  const size_t np = (size_t)W * H;
+  const int norm_pass = code8 ? 1 : 2; /* R2L for Int8, U2D for Int16 */
+  for (int n = 0; n < npasses; ++n) {
+    const int it = n / 4, k = n % 4;
+    if (k == norm_pass) normalize_slice(c, np, record ? NULL : refs[it], record ? refs[it] : NULL);
+    pass_k(c, W, H, wh, wv, k);
+    if (n + 1 == 4 * iters) break; /* the DT's last pass feeds the WTA */
+    store_slice(c, np, T, code8 && (k == 1 || k == 3), sat);
   }
 }
 
-static void v_pair(double* c, int W, int H, const double* wv) {
-  for (int x = 0; x < W; ++x) {
-    for (int y = 1; y < H; ++y) c[(ptrdiff_t)y * W + x] += wv[(ptrdiff_t)y * W + x] * c[(ptrdiff_t)(y - 1) * W + x];
-    for (int y = H - 2; y >= 0; --y)
-      c[(ptrdiff_t)y * W + x] += wv[(ptrdiff_t)(y + 1) * W + x] * c[(ptrdiff_t)(y + 1) * W + x];
+/* One disparity slice through the pass-pair form (already centred): the
+ * passes of the first npasses (a multiple of 2), storing after each pair but
+ * the DT's last. */
+static void int_slice_pairs(double* c, int W, int H, const double* wh, const double* wv, int iters, int npasses,
+                            double T, int code8, int64_t* sat) {
+  const size_t np = (size_t)W * H;
+  for (int n = 0; n < npasses; n += 2) {
+    pass_k(c, W, H, wh, wv, n % 4);
+    pass_k(c, W, H, wh, wv, n % 4 + 1);
+    if (n + 2 < 4 * iters) store_slice(c, np, T, code8, sat);
   }
 }
 
 int oracle_int_solve(const uint8_t* L, const uint8_t* R, int pitch, int W, int H, int D, int r, double sigma_s,
-                     double sigma_r, int iters, int guide_target, double T, int code8, double* final_hwd,
-                     int32_t* disp_hw) {
+                     double sigma_r, int iters, int guide_target, double T, int code8, int form, int npasses,
+                     double* final_hwd, int32_t* disp_hw, int64_t* saturated) {
   if (W < 1 || H < 1 || D < 1 || r < 0 || iters < 1 || pitch < W || !(T > 0.0)) return -1;
+  if (form != ORACLE_INT_PAPER && form != ORACLE_INT_PAIRS) return -1;
+  if (npasses == 0) npasses = 4 * iters;
+  if (npasses < 1 || npasses > 4 * iters || (form == ORACLE_INT_PAIRS && npasses % 2)) return -1;
   const size_t np = (size_t)W * H;
   double* c0 = (double*)malloc(np * sizeof(double));
   double* c = (double*)malloc(np * sizeof(double));
   double* best = (double*)malloc(np * sizeof(double));
   double* wh = (double*)malloc(np * sizeof(double));
   double* wv = (double*)malloc(np * sizeof(double));
-  int rc = -2;
-  if (c0 && c && best && wh && wv) {
+  double** refs = (double**)calloc((size_t)iters, sizeof(double*));
+  int64_t sat = 0;
+  int rc = -2, ok = c0 && c && best && wh && wv && refs;
+  for (int it = 0; ok && it < iters; ++it) ok = (refs[it] = (double*)malloc(np * sizeof(double))) != NULL;
+  if (ok) {
     rc = oracle_dt_weights(guide_target ? R : L, pitch, W, H, sigma_s, sigma_r, wh, wv);
     if (rc == 0) rc = oracle_zncc_cost_slice(L, R, pitch, W, H, r, 0, c0);
     for (int d = 0; rc == 0 && d < D; ++d) {
       rc = oracle_zncc_cost_slice(L, R, pitch, W, H, r, d, c);
       if (rc) break;
-      for (size_t p = 0; p < np; ++p) c[p] -= c0[p];
-      for (int it = 0; it < iters; ++it) {
-        h_pair(c, W, H, wh);
-        for (size_t p = 0; p < np; ++p) c[p] = quantize16(c[p], T, code8);
-        v_pair(c, W, H, wv);
-        if (it + 1 < iters)
-          for (size_t p = 0; p < np; ++p) c[p] = quantize16(c[p], T, code8);
+      if (form == ORACLE_INT_PAPER) {
+        /* d = 0 (= d_arb) comes first and records its normalization inputs */
+        int_slice_paper(c, W, H, wh, wv, iters, npasses, T, code8, refs, d == 0, &sat);
+      } else {
+        for (size_t p = 0; p < np; ++p) c[p] -= c0[p];
+        int_slice_pairs(c, W, H, wh, wv, iters, npasses, T, code8, &sat);
       }
       for (size_t p = 0; p < np; ++p) {
         if (final_hwd) final_hwd[p * D + d] = c[p];
@@ -370,6 +466,9 @@ int oracle_int_solve(const uint8_t* L, const uint8_t* R, int pitch, int W, int H
       }
     }
   }
+  if (saturated) *saturated = sat;
+  for (int it = 0; refs && it < iters; ++it) free(refs[it]);
+  free(refs);
   free(wv);
   free(wh);
   free(best);

@@ -352,67 +352,178 @@ def test_sgm_without_penalties_is_four_times_the_cost():
     assert np.array_equal(oracle.sgm_aggregate(one, 18.0, 185.0, 21.0), 4.0 * (21.0 * one))
 
 
+# ------------------------------------------- single DT passes
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_single_passes_constant_weight_closed_form(k):
+    """With the range term off every weight is K = exp(-1/sigma_s) (zero at the
+    line start), so one pass is a one-sided exponential sum along its line:
+    L: C_L(x) = sum_{u<=x} K^(x-u) C(u);  R: C_R(x) = sum_{v>=x} K^(v-x) C(v);
+    U and D the same along y -- written here as triangular matrices, not as a
+    recursion."""
+    rng = np.random.default_rng(40 + k)
+    H, W, ss = 7, 9, 3.0
+    K = math.exp(-1.0 / ss)
+    c = rng.uniform(-1.0, 2.0, (H, W))
+    wh, wv = oracle.dt_weights(np.zeros((H, W), np.uint8), ss, np.inf)
+    got = oracle.dt_passes(c, wh, wv, k, 1)
+    n = W if k < 2 else H
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    lower = np.where(j <= i, K ** np.abs(i - j), 0.0)   # rows: output index
+    M = lower if k in (0, 2) else lower.T
+    want = c @ M.T if k < 2 else M @ c
+    assert np.allclose(got, want, rtol=1e-13, atol=1e-13)
+
+
+def test_pass_sequence_is_the_sweep_sequence():
+    """Passes 0..4I-1 of the sequence (L, R, U, D, ...) are I sweeps, and a run
+    starting mid-sequence continues the cycle."""
+    rng = np.random.default_rng(44)
+    pr = scenes.bands_pair(W=23, H=17, D=8, seed=4, band_disps=(1, 4))
+    wh, wv = oracle.dt_weights(pr.left, 6.0, 0.2)
+    c = rng.uniform(0.0, 2.0, (17, 23))
+    for iters in (1, 2):
+        assert np.allclose(oracle.dt_passes(c, wh, wv, 0, 4 * iters), oracle.dt_slice(c, wh, wv, iters),
+                           rtol=1e-14, atol=1e-14)
+    half = oracle.dt_passes(oracle.dt_passes(c, wh, wv, 0, 3), wh, wv, 3, 3)
+    assert np.allclose(half, oracle.dt_passes(c, wh, wv, 0, 6), rtol=1e-14, atol=1e-14)
+
+
 # ------------------------------------------- integer volumes (Sec. IV-C) path
-def test_int_path_is_the_float_path_on_centred_costs_up_to_propagated_rounding():
-    """Each quantization between pass pairs moves a value by at most 1/(2T)
-    (no value here comes near saturation), and a later pass pair amplifies a
-    perturbation by at most G = (1+K)/(1-K), K = exp(-1/sigma_s).  So after I
-    sweeps (2I - 1 quantizations) the result is within
-    sum_{j=1}^{2I-1} G^j / (2T) of the float DT of the cost minus its d = 0
-    slice; with I = 1 that is G / (2T)."""
+def _q(v, T):
+    """sat16(round(T v)) as integers (round half to even)."""
+    return np.clip(np.rint(T * v), -32768, 32767)
+
+
+def _code(q):
+    return oracle.i8_decode(oracle.i8_encode(np.clip(q, -32768, 32767).astype(np.int16))).astype(np.float64)
+
+
+@pytest.mark.parametrize("code8", [False, True], ids=["i16", "i8"])
+def test_int_paths_without_aggregation(code8):
+    """With sigma_s = 1e-3 every DT weight exp(-1000 - ...) is exactly 0 in
+    double precision, so every pass is the identity and only the stores act.
+    Paper form: L2R stores Q(C) = sat16(round(T C)), R2L stores it again, and
+    the normalization subtracts the stored d_arb slice, so the result is
+    Q(C) - Q(C0) (Int16), or its 8-bit code (Int8, normalized and coded in
+    R2L); quantizing a stored value again changes nothing.  Pair form: the
+    centred cost is quantized once, Q(C - C0).  The two differ wherever the
+    rounding of a difference is not the difference of roundings.  T = 1e7
+    saturates most stores."""
+    pr = scenes.bands_pair(W=30, H=12, D=9, seed=6, band_disps=(1, 5))
+    D, r = 9, 1
+    c = oracle.zncc_cost(pr.left, pr.right, D, r)
+    wh, _ = oracle.dt_weights(pr.left, 1e-3, 0.2)
+    assert not wh.any()
+    for T in (21.0, 3.7, 1e7):
+        q = _q(c, T)
+        paper = np.clip(q - q[:, :, :1], -32768, 32767)
+        pairs = _q(c - c[:, :, :1], T)
+        if code8:
+            paper, pairs = _code(paper), _code(pairs)
+        for iters in (1, 2, 3):
+            got = oracle.int_solve(pr.left, pr.right, D, r, 1e-3, 0.2, iters, T=T, code8=code8, keep_volume=True)
+            assert np.array_equal(got.volume * T, paper) or np.allclose(got.volume * T, paper, rtol=0, atol=1e-6)
+            gp = oracle.int_solve(pr.left, pr.right, D, r, 1e-3, 0.2, iters, T=T, code8=code8, form="pairs",
+                                  keep_volume=True)
+            assert np.allclose(gp.volume * T, pairs, rtol=0, atol=1e-6)
+            assert (got.saturated > 0) == (T == 1e7), (T, got.saturated)
+        if T == 3.7:
+            assert not np.allclose(paper, pairs)   # the store points matter
+
+
+@pytest.mark.parametrize("code8", [False, True], ids=["i16", "i8"])
+def test_int_paper_form_store_points(code8):
+    """Invariants of the paper form's stored states (one sweep).  Before the
+    normalizing pass the states are T-scaled costs (non-negative multiples of
+    1/T, the d_arb slice not zero); the normalizing pass (U2D for Int16, R2L
+    for Int8) leaves the d_arb slice exactly zero from then on; R2L's output in
+    Int8 is an 8-bit code, so it is <= 0 and a decoded code; the DT's last
+    pass is not quantized."""
+    pr = scenes.bands_pair(W=48, H=30, D=10, seed=3, band_disps=(2, 6))
+    D, r, ss, sr, T = 10, 1, 5.0, 52.0 / 255.0, 21.0
+    norm = 2 if code8 else 3          # passes up to and including the normalizing one
+    for n in (1, 2, 3, 4):
+        v = oracle.int_solve(pr.left, pr.right, D, r, ss, sr, 1, T=T, code8=code8, keep_volume=True,
+                             npasses=n).volume
+        q = v * T
+        if n < 4:
+            assert np.allclose(q, np.rint(q), rtol=0, atol=1e-9), n
+        else:
+            assert (np.abs(q - np.rint(q)) > 1e-6).mean() > 0.5
+        if n < norm:
+            assert v.min() >= 0 and np.any(v[:, :, 0] != 0), n
+        else:
+            assert np.all(v[:, :, 0] == 0) and np.any(v[:, :, 1:] != 0), n
+        if code8 and n == 2:
+            qi = np.rint(q).astype(np.int64)
+            assert qi.max() <= 0 and (qi < 0).any()
+            assert np.array_equal(_code(qi), qi)
+
+
+def _dt_pass(e, wh, wv, k):
+    return oracle.dt_passes(e, wh, wv, k, 1)
+
+
+def _paper_error_field(wh, wv, iters, T):
+    """Componentwise bound on |Int16 paper form - DT(C - C0)|: every store
+    adds at most 1/(2T) (no saturation), a pass maps a bound field E to the
+    same pass of E (non-negative weights), and the U2D normalization, which
+    subtracts the d_arb slice's own value (carrying the same bound), doubles
+    it."""
+    e = np.zeros(wh.shape)
+    for n in range(4 * iters):
+        k = n % 4
+        if k == 2:
+            e = 2.0 * e
+        e = _dt_pass(e, wh, wv, k)
+        if n + 1 < 4 * iters:
+            e = e + 0.5 / T
+    return e
+
+
+def _pairs_error_field(wh, wv, iters, T):
+    """The same for the pair form: the centred cost is exact, each stored pair
+    output adds at most 1/(2T)."""
+    e = np.zeros(wh.shape)
+    for n in range(0, 4 * iters, 2):
+        e = _dt_pass(_dt_pass(e, wh, wv, n % 4), wh, wv, n % 4 + 1)
+        if n + 2 < 4 * iters:
+            e = e + 0.5 / T
+    return e
+
+
+@pytest.mark.parametrize("form", ["paper", "pairs"])
+def test_int16_path_within_propagated_rounding_of_the_float_path(form):
+    """Int16 in either form equals the float DT of the cost minus its d = 0
+    slice up to the propagated rounding of its stores (bound fields above),
+    as long as nothing saturates; and the rounding does show (err > 0)."""
     pr = scenes.bands_pair(W=40, H=24, D=12, seed=2, band_disps=(2, 7))
     D, r, sr, T = 12, 2, 52.0 / 255.0, 21.0
     c = oracle.zncc_cost(pr.left, pr.right, D, r)
     c = c - c[:, :, :1]
-    for ss, iters in ((5.0, 1), (2.0, 1), (2.0, 2)):  # the stored states stay far from saturation
-        K = np.exp(-1.0 / ss)
-        G = (1 + K) / (1 - K)
+    for ss, iters in ((5.0, 1), (2.0, 1), (2.0, 2), (20.0, 1)):
         wh, wv = oracle.dt_weights(pr.left, ss, sr)
-        _, got = oracle.int_solve(pr.left, pr.right, D, r, ss, sr, iters, T=T, keep_volume=True)
+        got = oracle.int_solve(pr.left, pr.right, D, r, ss, sr, iters, T=T, form=form, keep_volume=True)
+        assert got.saturated == 0, (ss, iters)
         want = oracle.dt_aggregate(c, wh, wv, iters)
-        assert np.abs(want).max() * T < 32767 / 4
-        bound = sum(G ** j for j in range(1, 2 * iters)) / (2 * T)
-        err = np.abs(got - want).max()
-        assert 0 < err <= bound + 1e-9, (iters, err, bound)
+        bound = (_paper_error_field if form == "paper" else _pairs_error_field)(wh, wv, iters, T)
+        err = np.abs(got.volume - want)
+        assert 0 < err.max() and np.all(err <= bound[:, :, None] * (1 + 1e-9) + 1e-12), \
+            (ss, iters, (err - bound[:, :, None]).max())
 
 
-def _quantized(v, T, code8):
-    q = np.clip(np.rint(T * v), -32768, 32767).astype(np.int16)
-    if code8:
-        q = oracle.i8_decode(oracle.i8_encode(q))
-    return q.astype(np.float64) / T
-
-
-@pytest.mark.parametrize("code8", [False, True])
-def test_int_path_without_aggregation_is_the_quantizer(code8):
-    """With sigma_s = 1e-3 every DT weight exp(-1000 - ...) is exactly 0 in
-    double precision, so each pass pair is the identity and the result is the
-    centred cost quantized once (quantizing a stored value again changes
-    nothing).  T = 1e7 drives the larger values into saturation at both ends."""
-    pr = scenes.bands_pair(W=30, H=12, D=9, seed=6, band_disps=(1, 5))
-    D, r = 9, 1
-    c = oracle.zncc_cost(pr.left, pr.right, D, r)
-    c = c - c[:, :, :1]
-    wh, _ = oracle.dt_weights(pr.left, 1e-3, 0.2)
-    assert not wh.any()
-    for T in (21.0, 3.7, 1e7):
-        for iters in (1, 2, 3):
-            _, got = oracle.int_solve(pr.left, pr.right, D, r, 1e-3, 0.2, iters, T=T, code8=code8,
-                                      keep_volume=True)
-            assert np.array_equal(got, _quantized(c, T, code8)), (T, iters)
-    _, sat = oracle.int_solve(pr.left, pr.right, D, r, 1e-3, 0.2, 1, T=1e7, code8=code8, keep_volume=True)
-    q = np.rint(sat * 1e7)
-    if code8:   # the 8-bit code keeps negative values only
-        assert (q == -32768).any() and np.all(q <= 0)
-    else:       # both ends of the int16 range are reached
-        assert (q == 32767).any() and (q == -32768).any()
-
-
-def test_int_path_leaves_the_last_pair_unquantized():
-    """The last pass pair's output goes to the WTA as is: it is not a multiple of
-    1/T, while a single sweep's only stored state (after the H pair) is."""
-    pr = scenes.bands_pair(W=48, H=30, D=10, seed=3, band_disps=(2, 6))
-    D, r, ss, sr, T = 10, 1, 5.0, 52.0 / 255.0, 21.0
-    _, got = oracle.int_solve(pr.left, pr.right, D, r, ss, sr, 1, T=T, keep_volume=True)
-    frac = np.abs(got * T - np.rint(got * T))
-    assert (frac > 1e-6).mean() > 0.5
+def test_int_paper_form_d_arb_slice_recorded_per_sweep():
+    """Several sweeps: the normalization of later sweeps subtracts a slice that
+    is already zero, so the d_arb slice stays exactly zero in every stored
+    state after the first normalization, and the Int8 path's D2U output of a
+    sweep that is not the last is a decoded 8-bit code like R2L's."""
+    pr = scenes.bands_pair(W=36, H=20, D=8, seed=9, band_disps=(1, 4))
+    D, r, ss, sr, T = 8, 1, 2.0, 52.0 / 255.0, 21.0
+    for code8 in (False, True):
+        for n in range(3, 12):
+            v = oracle.int_solve(pr.left, pr.right, D, r, ss, sr, 3, T=T, code8=code8, keep_volume=True,
+                                 npasses=n).volume
+            assert np.all(v[:, :, 0] == 0), (code8, n)
+            if code8 and n % 4 in (0, 2):   # after R2L or D2U
+                qi = np.rint(v * T).astype(np.int64)
+                assert np.array_equal(_code(qi), qi) and qi.max() <= 0, n

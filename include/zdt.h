@@ -13,8 +13,9 @@
  *   - Every pixel read is clamped to the image (replicate border); target
  *     columns x-d+i < 0 read column 0.
  *   - A cost volume is [H][W][D] with d fastest (element (x,y,d) at
- *     ((y*W + x)*D + d)), stored as float32, float16 or bfloat16
- *     (`vol_dtype`).  The cost is 1 - ZNCC in [0, 2].
+ *     ((y*W + x)*D + d)), stored as float32, float16, bfloat16, int16 or the
+ *     8-bit code of an int16 (`vol_dtype`, zdt_dtype below).  The cost is
+ *     1 - ZNCC in [0, 2] (times T for int16).
  *   - Pointers to images, volumes, disparities and workspace are DEVICE
  *     pointers owned by the caller; the library never frees or keeps them.
  *     `params` and the `applied_scale` output are HOST pointers.
@@ -45,13 +46,20 @@ typedef enum zdt_status {
 } zdt_status;
 
 /* Volume element types.  ZDT_I16 and ZDT_I8 are the paper's narrow integer
- * volumes (Sec. IV-C): the cost, made nearly zero-mean by subtracting the raw
- * cost at d_arb = 0 before the first DT pass (Eq. DT_new), times T = 21,
- * rounded to a saturated int16; ZDT_I8 stores that int16's 8-bit code (six
+ * volumes (Sec. IV-C) as its FastDT runs them (Sec. V-C, Table II): every DT
+ * state but the last is the cost times T = 21 rounded to an int16 (round half
+ * to even), as if each of the four passes stored its output; the states are
+ * made nearly zero-mean by Eq. DT_new with d_arb = 0, subtracting the pass
+ * input's d = 0 value at each pixel, in the first U2D pass for ZDT_I16 and
+ * in the first R2L pass for ZDT_I8.  ZDT_I8 stores the R2L output (and the
+ * output of every sweep but the last) as that int16's 8-bit code (six
  * significant bits plus a 2-bit position flag; only negative values are kept,
- * non-negative ones code to 0), four codes per 32-bit word along d.  They are
- * approximations for bandwidth (accuracy is reported, not bounded, against
- * the exact aggregation); the recursions still run in float32. */
+ * non-negative ones code to 0).  Volumes cross memory only between pass pairs;
+ * the rounding of the L2R and U2D outputs happens in registers.  The
+ * recursions run in float32.  They are approximations for bandwidth: the
+ * paper's choice of T bounds the states only for few passes, so stereo_solve
+ * refuses (ZDT_EUNSUPPORTED) parameters for which a stored state could leave
+ * the int16 range (bound: 2T, times 1/(1-K) per pass, plus 1/2 per store). */
 typedef enum zdt_dtype { ZDT_F32 = 0, ZDT_F16 = 1, ZDT_BF16 = 2, ZDT_I16 = 3, ZDT_I8 = 4 } zdt_dtype;
 
 /* flags */

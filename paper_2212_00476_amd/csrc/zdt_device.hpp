@@ -112,8 +112,9 @@ struct Elem<bf16> {
   }
 };
 
-// Integer cost volumes of Sec. IV-C: the (nearly zero-mean) cost scaled by T
-// and rounded to a 16-bit integer (i16v), or that integer's 8-bit code (i8c).
+// Integer cost volumes of Sec. IV-C: the cost scaled by T and rounded to a
+// 16-bit integer (i16v), or that integer's 8-bit code (i8c).  The passes run
+// on the T-scaled values, so a stored state is read back exactly.
 struct i16v {
   int16_t v;
 };
@@ -125,8 +126,10 @@ constexpr bool is_int_vol() {
   return std::is_same<T, i16v>::value || std::is_same<T, i8c>::value;
 }
 
-// float -> int16 with round-to-nearest-even and saturation.
-__device__ __forceinline__ int sat16(float v) { return (int)fminf(fmaxf(rintf(v), -32768.0f), 32767.0f); }
+// float -> int16 with round-to-nearest-even and saturation, as an integer and
+// as the float it stores exactly.
+__device__ __forceinline__ float rq16(float v) { return __builtin_amdgcn_fmed3f(rintf(v), -32768.0f, 32767.0f); }
+__device__ __forceinline__ int sat16(float v) { return (int)rq16(v); }
 
 // 8-bit code of a 16-bit value (Sec. IV-C): non-negative values give 0; a
 // negative value keeps the six bits below its leading ones at bit 9, 5 or 1
@@ -288,14 +291,33 @@ __host__ __device__ constexpr HLayout h_layout(int W, int R, int LPS, int pad, b
 
 enum HMode { kSums = 0, kCost = 1, kCostHPair = 2, kHPair = 3 };
 
+// The normalization of the integer volumes (Sec. IV-C, Eq. DT_new with
+// d_arb = 0) follows the FastDT of Sec. V-C: in the U2D pass for Int16, in the
+// R2L pass for Int8, subtracting the pass input's d = 0 value at each pixel.
+// Only the first sweep needs it (the d = 0 slice is zero from then on).  That
+// slice of the subtracted state lives in another workgroup (disparity chunk
+// 0), so it goes through a [H][W] map:
+//   kRefNone       no map
+//   kRefL2ROut     Int8 reference launch (chunk 0 only): lane d = 0 writes its
+//                  stored L2R output and the workgroup ends after the L pass
+//   kRefL2RIn      Int8 fused pass: the map is subtracted from the stored L2R
+//                  output before the R2L recursion
+//   kRefR2LOut     Int16 fused pass: lane d = 0 also writes its stored R2L
+//                  output to the map (the V pair of the first sweep subtracts it)
+// The reference launch runs the same code as the fused pass up to the L
+// output, so the subtracted values equal chunk 0's own bit for bit and the
+// normalized d = 0 slice is exactly zero.
+enum IntRef { kRefNone = 0, kRefL2ROut = 1, kRefL2RIn = 2, kRefR2LOut = 3 };
+
 struct HArgs {
   const uint8_t* left;
   const uint8_t* right;
   const uint8_t* guide;
   int pitch, W, H, D;
   float inv_sigma_s, range_coef, out_scale;
-  float in_scale;        // integer volumes: 1/T applied to every loaded value
-  const float* ref0;     // integer volumes: raw cost at d = 0 [H][W], subtracted before the first pass
+  float cost_scale;      // integer volumes: T, applied to the raw cost of the fused pass
+  int ref_role;          // integer volumes, first sweep: what `ref` is for (IntRef)
+  float* ref;            // [H][W] d_arb = 0 slice of a stored state (see IntRef)
   void* vol;
   int32_t* s_rt;
   int32_t* s_l;
@@ -319,7 +341,7 @@ struct HJob {
   void* vol;
   const float* g_in;
   float* g_out;
-  const float* ref0;
+  float* ref;
 };
 struct HJobs {
   HJob j[kMaxJobs];
@@ -667,14 +689,14 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
     a.vol = jb.vol;
     a.g_in = jb.g_in;
     a.g_out = jb.g_out;
-    a.ref0 = jb.ref0;
+    a.ref = jb.ref;
   }
   constexpr int NW = 2 * R + 1;  // window side
   constexpr int SPW = kWave / LPS;  // segments per wave
   constexpr bool kZncc = MODE != kHPair;
   constexpr bool kDT = MODE == kCostHPair || MODE == kHPair;
   constexpr bool kHalf = std::is_same<T, f16x>::value;  // gain-scaled FP16
-  constexpr bool kInt = is_int_vol<T>();                 // T-scaled, centred integer volume
+  constexpr bool kInt = is_int_vol<T>();                 // T-scaled integer volume (Sec. IV-C)
   static_assert(LPS == 64 || LPS == 32, "lanes per segment");
   constexpr uint32_t kBytes = sizeof(T);
   int y, chunk;
@@ -717,8 +739,10 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
     }
   }
   if constexpr (kInt && MODE == kCostHPair) {
-    const float* rr = a.ref0 + (size_t)y * W;  // the row's raw cost at d = 0
-    for (int x = threadIdx.x; x < W; x += blockDim.x) GI[x] = rr[x];
+    if (a.ref_role == kRefL2RIn) {
+      const float* rr = a.ref + (size_t)y * W;  // the row's stored L2R output at d = 0
+      for (int x = threadIdx.x; x < W; x += blockDim.x) GI[x] = rr[x];
+    }
   }
   __syncthreads();
 
@@ -834,12 +858,11 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
         }
       }
       fence();
-      const float* r0 = GI + x0;  // integer volumes: the d = 0 cost, subtracted (Eq. DT_new with d_arb = 0)
 #pragma unroll
       for (int k = 0; k < SEG; ++k) {
         const bool in = k < len;
         c[k] = zncc_cost_rec<R>(__float_as_uint(c[k]), lrec + k * RS, trec + k * RS);
-        if constexpr (kInt) c[k] -= r0[k];
+        if constexpr (kInt) c[k] *= a.cost_scale;
         const float w = wp[k];
         ell = in ? fmaf(w, ell, c[k]) : ell;
         P = in ? P * w : P;
@@ -850,10 +873,7 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < SEG; ++k) {
-        c[k] = Elem<T>::bload(vrs, voff, step_soff(k));
-        if constexpr (kInt) c[k] *= a.in_scale;
-      }
+      for (int k = 0; k < SEG; ++k) c[k] = Elem<T>::bload(vrs, voff, step_soff(k));
       __builtin_amdgcn_sched_barrier(0);
       const float* si = SI + x0;  // input scale factors at x0 + k
 #pragma unroll
@@ -875,17 +895,35 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
     const float carry = carry_in<false>(EX, EXS, seg, a.nseg, LPS, dloc, min(wave * SPW + SPW - 1, a.nseg - 1));
     reload_fence();
     // ---- loop B: exact L pass from the true carry; accumulate the carry-free R value at x0
+    // Integer volumes: the R pass reads the L2R output as stored (rounded to
+    // an int16; the L recursion itself runs on unrounded values), normalized
+    // in the first sweep of Int8 (R2L) by the stored d = 0 slice.
     float prev = carry, acc = 0.0f, pi = 1.0f;
+    const float* rl = GI + x0;  // Int8 first sweep: the L2R output's d = 0 slice at x0 + k
+    [[maybe_unused]] const bool sub_ref = kInt && MODE == kCostHPair && a.ref_role == kRefL2RIn;
 #pragma unroll
     for (int k = 0; k < SEG; ++k) {
       const bool in = k < len;
       const float w = wp[k];
       const float cl = fmaf(w, prev, c[k]);
-      c[k] = in ? cl : c[k];
+      float cv = cl;
+      if constexpr (kInt) {
+        cv = rq16(cl);
+        if (sub_ref) cv -= rl[k];
+      }
+      c[k] = in ? cv : c[k];
       prev = in ? cl : prev;
       if (k > 0) pi = in ? pi * w : pi;
-      acc = in ? fmaf(cl, pi, acc) : acc;
+      acc = in ? fmaf(cv, pi, acc) : acc;
       step_fence(k, prev, acc, pi);
+    }
+    if constexpr (kInt && MODE == kCostHPair) {
+      if (a.ref_role == kRefL2ROut) {  // Int8 reference launch: the stored L2R output at d = 0
+#pragma unroll
+        for (int k = 0; k < SEG; ++k)
+          if (d == 0 && k < len) a.ref[(size_t)y * W + x0 + k] = c[k];
+        return;
+      }
     }
     const float Q = pi * WH[x0 + len];
     EX2[seg * LPS + dloc] = acc;
@@ -910,6 +948,8 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
       next = in ? cr : next;
       const float v = scaled ? cr * so[k] : cr * a.out_scale;
       Elem<T>::bstore(vrs, in ? voff_st : kDrop, step_soff(k), v);
+      if constexpr (kInt && MODE == kCostHPair)
+        if (a.ref_role == kRefR2LOut && d == 0 && in) a.ref[(size_t)y * W + x0 + k] = rq16(v);
       step_fence(SEG - 1 - k, next);
     }
   }
@@ -922,13 +962,14 @@ struct VArgs {
   const uint8_t* guide;
   int pitch, W, H, D;
   float inv_sigma_s, range_coef, out_scale;
-  float in_scale;      // integer volumes: 1/T applied to every loaded value
+  int ref_sub;         // Int16 first sweep: subtract `ref` (U2D normalization, Eq. DT_new)
   void* vol;
   const float* g_in;   // FP16 working volume: gain map [H][W] of the stored input
   float* g_out;        // and of the output (not for the WTA pass)
   int32_t* disp;       // WTA with a single chunk: final disparity
   float* part_val;     // WTA with several chunks: [chunk][W][H] minimum (column-major)
   int32_t* part_idx;   // and its disparity
+  const float* ref;    // Int16: [H][W] stored R2L output at d = 0 (written by the first H pair)
   int segl, nseg;      // segment length and number of segments of a column
   int nchunks;         // disparity chunks of LPS lanes
 };
@@ -941,16 +982,18 @@ struct VJob {
   int32_t* disp;
   float* part_val;
   int32_t* part_idx;
+  const float* ref;
 };
 struct VJobs {
   VJob j[kMaxJobs];
 };
 
 // WV[H+1] (+ SEG spare entries), EX/EX2 [32 segments x 32 lanes or 16 x 64],
-// EXS/EXS2 [kMaxSegs], and for the FP16 working volume GI, GO [H + SEG], the
-// column's gains before and after the pair.
-__host__ __device__ inline int v_lds_words(int H, int SEG, bool scaled) {
-  return (H + 1 + SEG) + 2 * (kMaxWaves * kWave + kMaxSegs) + (scaled ? 3 * (H + SEG) : 0);
+// EXS/EXS2 [kMaxSegs], and for the FP16 working volume GI, GO, SI [H + SEG],
+// the column's gains before and after the pair and the input scale factors;
+// integer volumes use GI for the column of the normalization map.
+__host__ __device__ inline int v_lds_words(int H, int SEG, bool scaled, bool ints) {
+  return (H + 1 + SEG) + 2 * (kMaxWaves * kWave + kMaxSegs) + (scaled ? 3 * (H + SEG) : (ints ? H + SEG : 0));
 }
 
 // Order-preserving 32-bit key of a float (-0 folded onto +0) and its inverse.
@@ -1088,6 +1131,7 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs args, VJobs jobs) {
     a.disp = jb.disp;
     a.part_val = jb.part_val;
     a.part_idx = jb.part_idx;
+    a.ref = jb.ref;
   }
   constexpr bool kHalf = std::is_same<T, f16x>::value;  // gain-scaled FP16
   constexpr bool kInt = is_int_vol<T>();                 // T-scaled integer volume
@@ -1126,6 +1170,9 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs args, VJobs jobs) {
       GI[y] = g;
       SI[y] = gain_scale_in(g);
     }
+  if constexpr (kInt)
+    if (a.ref_sub)
+      for (int y = threadIdx.x; y < H; y += blockDim.x) GI[y] = a.ref[(size_t)y * W + x];
   for (int y = threadIdx.x; y <= H; y += blockDim.x)
     WV[y] = (y >= 1 && y < H) ? dt_weight(a.guide[(size_t)y * a.pitch + x], a.guide[(size_t)(y - 1) * a.pitch + x],
                                           a.inv_sigma_s, a.range_coef)
@@ -1161,18 +1208,20 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs args, VJobs jobs) {
 
   float c[SEG];
 #pragma unroll
-  for (int k = 0; k < SEG; ++k) {
-    c[k] = Elem<T>::bload(vrs, voff, step_off(k));
-    if constexpr (kInt) c[k] *= a.in_scale;
-  }
+  for (int k = 0; k < SEG; ++k) c[k] = Elem<T>::bload(vrs, voff, step_off(k));
   __builtin_amdgcn_sched_barrier(0);
-  // ---- loop A: carry-free U pass (decoding scaled FP16 values on the way)
+  // ---- loop A: carry-free U pass (decoding scaled FP16 values on the way;
+  // Int16's first sweep subtracts the stored R2L output's d = 0 slice first)
   float ell = 0.0f, P = 1.0f;
+  const float* rf = GI + y0;
+  [[maybe_unused]] const bool sub_ref = kInt && a.ref_sub;
 #pragma unroll
   for (int k = 0; k < SEG; ++k) {
     const bool in = k < len;
     const float w = wp[k];
     if constexpr (scaled) c[k] *= si[k];
+    if constexpr (kInt)
+      if (sub_ref) c[k] -= rf[k];
     ell = in ? fmaf(w, ell, c[k]) : ell;
     P = in ? P * w : P;
     step_fence(k, ell, P);
@@ -1188,7 +1237,8 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs args, VJobs jobs) {
     prev = carry_in<false>(EX, EXS, seg, a.nseg, LPS, dloc, min(wave * SPW + SPW - 1, a.nseg - 1));
   }
   reload_fence();
-  // ---- loop B: exact U pass; carry-free D value at y0
+  // ---- loop B: exact U pass; carry-free D value at y0 (integer volumes: the
+  // D pass reads the U2D output as stored, rounded to an int16)
   float acc = 0.0f, pi = 1.0f;
 #pragma unroll
   for (int k = 0; k < SEG; ++k) {
@@ -1196,9 +1246,10 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs args, VJobs jobs) {
     const float w = wp[k];
     if (k > 0) pi = in ? pi * w : pi;
     const float cu = fmaf(w, prev, c[k]);
-    c[k] = in ? cu : c[k];
+    const float cv = kInt ? rq16(cu) : cu;
+    c[k] = in ? cv : c[k];
     prev = in ? cu : prev;
-    acc = in ? fmaf(cu, pi, acc) : acc;
+    acc = in ? fmaf(cv, pi, acc) : acc;
     step_fence(k, prev, acc, pi);
   }
   const float Q = pi * WV[y0 + len];
@@ -1338,111 +1389,6 @@ struct WJob {
 struct WJobs {
   WJob j[kMaxJobs];
 };
-// The raw cost at d = 0 of every pixel: the centring reference of the integer
-// volumes (Eq. DT_new with d_arb = 0).  The arithmetic is that of the fused
-// cost pass, so the centred d = 0 slice comes out exactly zero.  One workgroup
-// per row packs both images' window columns (the target column at d = 0 is the
-// reference column), then each thread forms the five window sums S_R, S_RR,
-// S_T, S_TT and S_RT of kStatRun consecutive positions from column sums.
-struct Ref0Job {
-  const uint8_t* left;
-  const uint8_t* right;
-  float* ref0;  // [H][W]
-};
-struct Ref0Jobs {
-  Ref0Job j[kMaxJobs];
-};
-constexpr int kRef0Threads = 256;
-__host__ __device__ constexpr int ref0_cols(int W, int R) { return W + 2 * R + kStatRun - 1; }
-__host__ __device__ constexpr int ref0_lds_words(int W, int R) { return 2 * packs_of(R) * ref0_cols(W, R); }
-
-template <int R>
-__global__ __launch_bounds__(kRef0Threads) void zncc_ref0_kernel(Ref0Jobs jobs, int pitch, int W, int H) {
-  extern __shared__ uint32_t smem[];
-  constexpr int NP = packs_of(R);
-  constexpr int NW = 2 * R + 1;
-  constexpr uint32_t N = NW * NW;
-  constexpr int NC = kStatRun + 2 * R;
-  const Ref0Job& jb = jobs.j[blockIdx.z];
-  const int y = blockIdx.x;
-  const int ncol = ref0_cols(W, R);
-  uint32_t* LPK = smem;              // [ncol][NP] packed reference columns
-  uint32_t* TPK = smem + ncol * NP;  // and target columns
-  const uint8_t* lrow[NW];
-  const uint8_t* trow[NW];
-#pragma unroll
-  for (int q = 0; q < NW; ++q) {
-    const size_t off = (size_t)clampi(y - R + q, 0, H - 1) * pitch;
-    lrow[q] = jb.left + off;
-    trow[q] = jb.right + off;
-  }
-  for (int i = threadIdx.x; i < ncol; i += blockDim.x) {
-    const int col = clampi(i - R, 0, W - 1);
-#pragma unroll
-    for (int k = 0; k < NP; ++k) {
-      uint32_t pl = 0, pt = 0;
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (4 * k + j < NW) {
-          pl |= (uint32_t)lrow[4 * k + j][col] << (8 * j);
-          pt |= (uint32_t)trow[4 * k + j][col] << (8 * j);
-        }
-      LPK[i * NP + k] = pl;
-      TPK[i * NP + k] = pt;
-    }
-  }
-  __syncthreads();
-  const int nr = (W + kStatRun - 1) / kStatRun;
-  for (int u = threadIdx.x; u < nr; u += blockDim.x) {
-    const int p0 = u * kStatRun;
-    // column sums of I_R, I_R^2, I_T, I_T^2 and I_R I_T over the window rows
-    uint32_t cl[NC], cll[NC], ct[NC], ctt[NC], clt[NC];
-#pragma unroll
-    for (int j = 0; j < NC; ++j) {
-      cl[j] = cll[j] = ct[j] = ctt[j] = clt[j] = 0;
-#pragma unroll
-      for (int k = 0; k < NP; ++k) {
-        const uint32_t l = LPK[(p0 + j) * NP + k], t = TPK[(p0 + j) * NP + k];
-        cl[j] = __builtin_amdgcn_udot4(l, 0x01010101u, cl[j], false);
-        cll[j] = __builtin_amdgcn_udot4(l, l, cll[j], false);
-        ct[j] = __builtin_amdgcn_udot4(t, 0x01010101u, ct[j], false);
-        ctt[j] = __builtin_amdgcn_udot4(t, t, ctt[j], false);
-        clt[j] = __builtin_amdgcn_udot4(l, t, clt[j], false);
-      }
-    }
-    uint32_t sl = 0, sll = 0, st = 0, stt = 0, slt = 0;
-#pragma unroll
-    for (int j = 0; j < NW; ++j) {
-      sl += cl[j];
-      sll += cll[j];
-      st += ct[j];
-      stt += ctt[j];
-      slt += clt[j];
-    }
-#pragma unroll
-    for (int i = 0; i < kStatRun; ++i) {
-      if (i > 0) {
-        sl += cl[i + 2 * R] - cl[i - 1];
-        sll += cll[i + 2 * R] - cll[i - 1];
-        st += ct[i + 2 * R] - ct[i - 1];
-        stt += ctt[i + 2 * R] - ctt[i - 1];
-        slt += clt[i + 2 * R] - clt[i - 1];
-      }
-      const int p = p0 + i;
-      if (p < W) {
-        // as stage_zncc and zncc_cost_rec
-        const int vl = (int)(__umul24(N, sll) - __umul24(sl, sl));
-        const int vt = (int)(__umul24(N, stt) - __umul24(st, st));
-        const float il = vl > 0 ? __builtin_amdgcn_rsqf((float)vl) : 0.0f;
-        const float it = vt > 0 ? __builtin_amdgcn_rsqf((float)vt) : 0.0f;
-        const int num = (int)(__umul24(N, slt) + (uint32_t)__mul24(-(int)sl, (int)st));
-        const float c = fmaf(-(float)num, il * it, 1.0f);
-        jb.ref0[(size_t)y * W + p] = fminf(fmaxf(c, 0.0f), 2.0f);
-      }
-    }
-  }
-}
-
 // The partial minima are stored column-major ([chunk][x][y]: a V-pass wave's
 // pixels are consecutive rows of one column); a 32 x 32 tile is combined with
 // reads along y, transposed through LDS and written along x.  Block 32 x 8.

@@ -17,7 +17,8 @@ int run_h(const HArgs& a, const HJobs& jobs, int n, hipStream_t s) {
   const int spw = kWave / LPS;
   const int nw = (a.nseg + spw - 1) / spw;
   HArgs b = a;
-  b.nchunks = (a.D + LPS - 1) / LPS;
+  // the Int8 reference launch covers disparity chunk 0 only
+  b.nchunks = a.ref_role == kRefL2ROut ? 1 : (a.D + LPS - 1) / LPS;
   dim3 grid(b.nchunks, a.H, n);
   if constexpr ((MODE == kCostHPair || MODE == kHPair) && sizeof(T) == 2) {
     // 1-D grid (per job) with the chunk pairs of a row on one XCD (see h_tile)
@@ -74,7 +75,7 @@ int run_v(const VArgs& a, const VJobs& jobs, int n, hipStream_t s) {
   }
   const int nw = a.nseg / (kWave / LPS);
   return launch(WTA ? "dt_vpair_wta" : "dt_vpair", vpass_kernel<SEG, FULL, T, LPS, WTA>, grid, dim3(kWave * nw),
-                (size_t)v_lds_words(a.H, SEG, std::is_same<T, f16x>::value) * 4, s, b, jobs);
+                (size_t)v_lds_words(a.H, SEG, std::is_same<T, f16x>::value, is_int_vol<T>()) * 4, s, b, jobs);
 }
 
 template <typename T, bool WTA>

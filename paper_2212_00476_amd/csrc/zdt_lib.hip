@@ -305,7 +305,8 @@ HArgs make_hargs(const zdt_params* p, float out_scale) {
   a.inv_sigma_s = 1.0f / p->sigma_s;
   a.range_coef = range_coef(p);
   a.out_scale = out_scale;
-  a.in_scale = 1.0f;
+  a.cost_scale = 1.0f;
+  a.ref_role = kRefNone;
   return a;
 }
 
@@ -318,7 +319,7 @@ VArgs make_vargs(const zdt_params* p, float out_scale) {
   a.inv_sigma_s = 1.0f / p->sigma_s;
   a.range_coef = range_coef(p);
   a.out_scale = out_scale;
-  a.in_scale = 1.0f;
+  a.ref_sub = 0;
   return a;
 }
 
@@ -347,26 +348,6 @@ int launch_h(const zdt_params* p, int dtype, int mode, bool scaled, HArgs a, con
     case ZDT_I8: return dispatch_h_i8(mode, R, sp.seg, lps, a, t, n, s);
   }
   return fail(ZDT_EINVAL, "bad dtype %d", dtype);
-}
-
-// The d = 0 raw cost of n pairs (integer volumes' centring reference).
-template <int R>
-int launch_ref0_r(const zdt_params* p, const Ref0Jobs& t, int n, hipStream_t s) {
-  return launch("zncc_ref0", zncc_ref0_kernel<R>, dim3(p->height, 1, n), dim3(kRef0Threads),
-                (size_t)ref0_lds_words(p->width, R) * 4, s, t, p->pitch, p->width, p->height);
-}
-int launch_ref0(const zdt_params* p, const Ref0Jobs& t, int n, hipStream_t s) {
-  switch (p->radius) {
-    case 0: return launch_ref0_r<0>(p, t, n, s);
-    case 1: return launch_ref0_r<1>(p, t, n, s);
-    case 2: return launch_ref0_r<2>(p, t, n, s);
-    case 3: return launch_ref0_r<3>(p, t, n, s);
-    case 4: return launch_ref0_r<4>(p, t, n, s);
-    case 5: return launch_ref0_r<5>(p, t, n, s);
-    case 6: return launch_ref0_r<6>(p, t, n, s);
-    case 7: return launch_ref0_r<7>(p, t, n, s);
-  }
-  return fail(ZDT_EUNSUPPORTED, "zncc_ref0: radius %d", p->radius);
 }
 
 int launch_v(const zdt_params* p, bool scaled, bool wta, VArgs a, const VJobs& t, int n, const Plan& pl,
@@ -402,7 +383,7 @@ int dispatch_wta(int dtype, const void* vol, int npix, int D, int32_t* disp, hip
 // disparity chunks (one V lane per disparity; chunks of 32 or 64 disparities
 // depending on the plan, so the size covers 32).
 struct WsLayout {
-  size_t gain_a, gain_b, ref0, part_val, part_idx, total;
+  size_t gain_a, gain_b, ref, part_val, part_idx, total;
 };
 size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 int wta_chunks(const zdt_params* p, int v_lanes) { return (p->max_disp + v_lanes - 1) / v_lanes; }
@@ -416,8 +397,8 @@ WsLayout ws_layout(const zdt_params* p) {
     L.gain_b = o;
     o += align256(npix * sizeof(float));
   }
-  if (int_vol(p->vol_dtype) && p->dt_iters > 0) {  // the raw cost at d = 0 (centring reference)
-    L.ref0 = o;
+  if (int_vol(p->vol_dtype) && p->dt_iters > 0) {  // the d = 0 slice the first sweep normalizes by
+    L.ref = o;
     o += align256(npix * sizeof(float));
   }
   if (p->dt_iters > 0 && wta_chunks(p, 32) > 1) {
@@ -446,7 +427,7 @@ int solve_group(const zdt_params* p, const JobPtrs* jobs, int n, hipStream_t s) 
   const Plan pl = plan_for(p);
   const WsLayout L = ws_layout(p);
   const bool scaled = p->vol_dtype == ZDT_F16;  // gain-scaled FP16 working volume
-  const bool ints = int_vol(p->vol_dtype);       // T-scaled, centred integer volume
+  const bool ints = int_vol(p->vol_dtype);       // T-scaled integer volume (Sec. IV-C)
   const int vchunks = wta_chunks(p, pl.v_lanes);
   const bool multi = vchunks > 1;
   HJobs ht{};
@@ -459,32 +440,39 @@ int solve_group(const zdt_params* p, const JobPtrs* jobs, int n, hipStream_t s) 
     float* gb = scaled ? (float*)((char*)j.ws + L.gain_b) : nullptr;
     float* pv = multi ? (float*)((char*)j.ws + L.part_val) : nullptr;
     int32_t* pi = multi ? (int32_t*)((char*)j.ws + L.part_idx) : nullptr;
-    const float* r0 = ints ? (const float*)((char*)j.ws + L.ref0) : nullptr;
-    ht.j[i] = {j.left, j.right, guide, j.vol, gb, ga, r0};                    // H pairs: B -> A
-    vt.j[i] = {guide, j.vol, ga, gb, multi ? nullptr : j.disp, pv, pi};      // V pairs: A -> B
+    float* rf = ints ? (float*)((char*)j.ws + L.ref) : nullptr;
+    ht.j[i] = {j.left, j.right, guide, j.vol, gb, ga, rf};                    // H pairs: B -> A
+    vt.j[i] = {guide, j.vol, ga, gb, multi ? nullptr : j.disp, pv, pi, rf};  // V pairs: A -> B
     wt.j[i] = {pv, pi, j.disp};
   }
   // An FP16 working volume is scaled per pixel by its gain and needs no
-  // global scale; integer volumes store T times the value; the other types
-  // take the (1-K)-per-pass normalisation.
-  const float sc = scaled ? 1.0f : (ints ? kIntScale : pair_scale(p));
+  // global scale; integer volumes hold T times the value (the fused pass
+  // scales the raw cost); the other types take the (1-K)-per-pass
+  // normalisation.
+  const float sc = (scaled || ints) ? 1.0f : pair_scale(p);
   HArgs ha = make_hargs(p, sc);
   VArgs va = make_vargs(p, sc);
-  ha.in_scale = va.in_scale = ints ? 1.0f / kIntScale : 1.0f;
+  if (ints) ha.cost_scale = kIntScale;
   int rc = ZDT_OK;
-  if (ints) {
-    // centring reference (Eq. DT_new with d_arb = 0): the raw cost slice d = 0,
-    // subtracted from every raw cost before the first pass.  The passes are
-    // linear and map the zero slice to zero, so every later stage stays centred.
-    Ref0Jobs rt{};
-    for (int i = 0; i < n; ++i) rt.j[i] = {jobs[i].left, jobs[i].right, const_cast<float*>(ht.j[i].ref0)};
-    rc = launch_ref0(p, rt, n, s);
-  }
   // sweep 1: cost fused with L, R; then U, D.  Sweeps 2..I: L, R; U, D.  The
-  // last U, D pair carries the WTA and writes no volume.
+  // last U, D pair carries the WTA and writes no volume.  Integer volumes
+  // follow the FastDT of Sec. V-C (see IntRef): the first sweep's Int8 R2L
+  // subtracts the L2R output's d = 0 slice, taken by a reference launch over
+  // disparity chunk 0; Int16's first U2D subtracts the R2L output's d = 0
+  // slice, written by the fused pass.
+  if (ints && p->vol_dtype == ZDT_I8) {
+    HArgs hr = ha;
+    hr.ref_role = kRefL2ROut;
+    rc = launch_h(p, p->vol_dtype, kCostHPair, scaled, hr, ht, n, pl, s);
+    ha.ref_role = kRefL2RIn;
+  } else if (ints) {
+    ha.ref_role = kRefR2LOut;
+  }
   if (rc == ZDT_OK) rc = launch_h(p, p->vol_dtype, kCostHPair, scaled, ha, ht, n, pl, s);
+  ha.ref_role = kRefNone;
   for (int it = 0; rc == ZDT_OK && it < p->dt_iters; ++it) {
     if (it > 0 && (rc = launch_h(p, p->vol_dtype, kHPair, scaled, ha, ht, n, pl, s))) break;
+    va.ref_sub = (it == 0 && p->vol_dtype == ZDT_I16) ? 1 : 0;
     rc = launch_v(p, scaled, it + 1 == p->dt_iters, va, vt, n, pl, s);
   }
   if (rc == ZDT_OK && multi) {
@@ -507,10 +495,34 @@ int solve_raw(const zdt_params* p, const JobPtrs& j, hipStream_t s) {
   return dispatch_wta(p->vol_dtype, j.vol, p->width * p->height, p->max_disp, j.disp, s);
 }
 
+// Integer volumes keep every DT state but the last as a T-scaled int16.  The
+// raw costs lie in [0, 2]; a pass with weights in [0, K] multiplies the largest
+// magnitude by at most 1/(1-K); the normalization subtracts one non-negative
+// state from another, which cannot grow it; a store adds at most 1/2.  A
+// stored state can therefore leave the int16 range only if
+//   s_n = s_{n-1} / (1-K) + 1/2,  s_0 = 2 T,
+// exceeds 32767 for some n < 4 I (the DT's last pass is not stored).  Such
+// parameters are refused rather than saturated silently.
+int check_int_range(const zdt_params* p, const char* who) {
+  if (!int_vol(p->vol_dtype) || p->dt_iters < 1) return ZDT_OK;
+  const double g = 1.0 / one_minus_k(p);
+  double b = 2.0 * kIntScale;
+  for (int n = 1; n < 4 * p->dt_iters; ++n) {
+    b = b * g + 0.5;
+    if (b > 32767.0)
+      return fail(ZDT_EUNSUPPORTED,
+                  "%s: with sigma_s = %g and %d sweeps a stored int16 state could reach %.4g after %d passes "
+                  "(T = %g); integer volumes need that bound below 32767", who, p->sigma_s, p->dt_iters, b, n,
+                  (double)kIntScale);
+  }
+  return ZDT_OK;
+}
+
 int check_job(const zdt_params* p, const uint8_t* left, const uint8_t* right, const int32_t* disp, const void* vol,
               const void* ws, const char* who) {
   int rc = check_params(p, who);
   if (rc) return rc;
+  if ((rc = check_int_range(p, who))) return rc;
   if (!left || !right || !disp || !vol) return fail(ZDT_EINVAL, "%s: NULL image, disparity or volume pointer", who);
   if (p->vol_dtype == ZDT_I8 && p->dt_iters == 0)
     return fail(ZDT_EUNSUPPORTED, "%s: 8-bit coded volumes need dt_iters >= 1 (raw costs code to zero)", who);

@@ -73,6 +73,34 @@ def test_argument_validation_without_device():
         assert lib.stereo_solve(ctypes.byref(p), None, None, None, None, None, None) == _lib.ZDT_EUNSUPPORTED
 
 
+def _int_state_bound(sigma_s, iters, T=21.0):
+    """Largest magnitude a stored int16 state of the integer volumes can reach:
+    2T after the T-scaled raw cost, times 1/(1-K) per pass, plus 1/2 per
+    store, over the 4 I - 1 stored states."""
+    g = 1.0 / -math.expm1(-1.0 / sigma_s)
+    b, worst = 2.0 * T, 0.0
+    for _ in range(4 * iters - 1):
+        b = b * g + 0.5
+        worst = max(worst, b)
+    return worst
+
+
+@pytest.mark.parametrize("dtype", [zdt.ZDT_I16, zdt.ZDT_I8], ids=["i16", "i8"])
+def test_integer_volumes_refused_where_a_state_could_saturate(dtype):
+    """Integer volumes are refused (ZDT_EUNSUPPORTED, before the pointers are
+    looked at) exactly where the bound on a stored int16 state exceeds 32767:
+    sigma_s = 20 with three sweeps (the benchmark's DT) and even one sweep;
+    the paper's sigma_s = 5 with one sweep is accepted (NULL pointers then
+    give ZDT_EINVAL)."""
+    lib = zdt.load()
+    for ss, iters in ((20.0, 3), (20.0, 1), (5.0, 1), (5.0, 2), (2.0, 2), (8.0, 1), (1.0, 3), (9.0, 1)):
+        p = zdt.params(64, 32, 16, 4, sigma_s=ss, dt_iters=iters, vol_dtype=dtype)
+        rc = lib.stereo_solve(ctypes.byref(p), None, None, None, None, None, None)
+        want = _lib.ZDT_EUNSUPPORTED if _int_state_bound(ss, iters) > 32767 else _lib.ZDT_EINVAL
+        assert rc == want, (ss, iters, rc, _int_state_bound(ss, iters))
+    assert _int_state_bound(20.0, 3) > 32767 and _int_state_bound(5.0, 1) < 32767
+
+
 def test_reserved_fields_must_be_zero():
     p = zdt.params(64, 32, 16)
     p.reserved[2] = 1

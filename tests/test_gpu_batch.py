@@ -23,7 +23,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 import paper_2212_00476_amd as zdt  # noqa: E402
 
-DT_REL = 3e-5
+DT_REL = 1e-5   # the FP32 aggregated-volume bar (derivation in test_gpu_parity.py)
 ORACLE_THREADS = min(16, os.cpu_count() or 1)
 
 
@@ -42,7 +42,10 @@ def pair_for(W, H, D, seed=0):
 
 class Job:
     def __init__(self, W, H, D, r, dtype, iters, seed):
-        self.p = zdt.params(W, H, D, r, dt_iters=iters, vol_dtype=dtype)
+        # the integer volumes take the paper's sigma_s = 5 (at sigma_s = 20 a
+        # stored int16 state could saturate, and such calls are refused)
+        ss = 5.0 if dtype in (zdt.ZDT_I16, zdt.ZDT_I8) else 20.0
+        self.p = zdt.params(W, H, D, r, sigma_s=ss, dt_iters=iters, vol_dtype=dtype)
         pr = pair_for(W, H, D, seed)
         self.left, self.right = dev(pr.left), dev(pr.right)
         self.disp = torch.full((H, W), -1, dtype=torch.int32, device="cuda")

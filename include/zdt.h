@@ -124,6 +124,22 @@ int wta_disparity(const zdt_params* params, const void* cost_hwd, int32_t* disp_
 int stereo_solve(const zdt_params* params, const uint8_t* left, const uint8_t* right, int32_t* disp_hw,
                  void* vol_hwd, void* ws, void* stream);
 
+/* stereo_solve() for callers that cannot allocate: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * workspace comes from an array of ZDT_STATIC_WS_BYTES bytes that the library
+ * holds on each GPU it runs on (until the process ends); the caller passes the
+ * images, the disparity output and the working volume (zdt_volume_size()
+ * bytes) as for stereo_solve().  Parameters whose zdt_workspace_size() exceeds
+ * ZDT_STATIC_WS_BYTES give ZDT_EUNSUPPORTED (1280x384 with D = 128 fits in
+ * every volume type).  The call makes no device or host allocation (the
+ * array's device address is looked up once per GPU) and records no timing
+ * events.  Every call on one GPU shares that GPU's array: calls that may
+ * overlap on one GPU (other streams or threads) race and must be ordered by
+ * the caller.  Nothing in the array needs to start at any value. */
+#define ZDT_STATIC_WS_BYTES (32u << 20)
+int stereo_solve_static_ws(const zdt_params* params, const uint8_t* left, const uint8_t* right, int32_t* disp_hw,
+                           void* vol_hwd, void* stream);
+
 /* One pair of a batch: its parameters and caller-owned device buffers, as for
  * stereo_solve() (vol: zdt_volume_size(&params) bytes, ws:
  * zdt_workspace_size(&params) bytes).  Jobs of one batch must not share a

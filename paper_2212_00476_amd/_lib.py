@@ -19,7 +19,7 @@ ZDT_FLAG_NORMALIZE = 1
 ZDT_FLAG_GUIDE_TARGET = 2
 
 EXPORTED = ("zdt_workspace_size", "zdt_volume_size", "zncc_cost_volume", "dt_aggregate", "wta_disparity",
-            "stereo_solve", "stereo_solve_batch", "zdt_plan_candidates", "zdt_get_plan", "zdt_set_plan",
+            "stereo_solve", "stereo_solve_static_ws", "stereo_solve_batch", "zdt_plan_candidates", "zdt_get_plan", "zdt_set_plan",
             "zdt_autotune", "zncc_window_sums", "zdt_i8_codec", "sgm_aggregate", "sgm_disparity",
             "stereo_solve_sgm", "zdt_integral_workspace_size", "zncc_window_sums_integral", "zdt_last_error", "zdt_profile_enable", "zdt_profile_collect", "zdt_profile_entry")
 
@@ -70,6 +70,7 @@ def load():
     lib.dt_aggregate.argtypes = [PP, P, P, ctypes.POINTER(ctypes.c_double), P]
     lib.wta_disparity.argtypes = [PP, P, P, P]
     lib.stereo_solve.argtypes = [PP, P, P, P, P, P, P]
+    lib.stereo_solve_static_ws.argtypes = [PP, P, P, P, P, P]
     lib.zncc_window_sums.argtypes = [PP, P, P, P, P, P, P, P, P]
     lib.stereo_solve_batch.argtypes = [ctypes.POINTER(ZdtJob), ctypes.c_int32, P]
     PL = ctypes.POINTER(ZdtPlan)
@@ -89,7 +90,8 @@ def load():
     lib.zdt_profile_enable.argtypes = [ctypes.c_int]
     lib.zdt_profile_entry.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
-    for f in ("zncc_cost_volume", "dt_aggregate", "wta_disparity", "stereo_solve", "stereo_solve_batch",
+    for f in ("zncc_cost_volume", "dt_aggregate", "wta_disparity", "stereo_solve", "stereo_solve_static_ws",
+              "stereo_solve_batch",
               "zdt_plan_candidates", "zdt_get_plan", "zdt_set_plan", "zdt_autotune", "zncc_window_sums", "zdt_i8_codec",
               "sgm_aggregate", "sgm_disparity", "stereo_solve_sgm", "zncc_window_sums_integral", "zdt_profile_enable",
               "zdt_profile_collect",
@@ -149,6 +151,14 @@ def wta_disparity(p, cost, disp, stream=None):
 def stereo_solve(p, left, right, disp, vol, ws=None, stream=None):
     _check("stereo_solve", load().stereo_solve(ctypes.byref(p), _ptr(left), _ptr(right), _ptr(disp), _ptr(vol),
                                                _ptr(ws), _stream(stream)))
+
+
+def stereo_solve_static_ws(p, left, right, disp, vol, stream=None):
+    _check("stereo_solve_static_ws", load().stereo_solve_static_ws(ctypes.byref(p), _ptr(left), _ptr(right),
+                                                                   _ptr(disp), _ptr(vol), _stream(stream)))
+
+
+STATIC_WS_BYTES = 32 << 20
 
 
 def stereo_solve_batch(jobs, stream=None):

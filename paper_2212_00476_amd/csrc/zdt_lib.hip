@@ -75,7 +75,11 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
+// Set while a call that must not allocate is enqueueing: no timing events then.
+thread_local bool g_no_alloc = false;
+
 bool prof_begin(ProfRec& rec, hipStream_t s) {
+  if (g_no_alloc) return false;
   {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     if (!g_prof_on) return false;
@@ -535,6 +539,41 @@ int check_job(const zdt_params* p, const uint8_t* left, const uint8_t* right, co
 
 zdt_plan to_c(const Plan& pl) { return zdt_plan{pl.h_lanes, pl.h_seg, pl.v_lanes, pl.v_seg}; }
 
+// ---- the workspace of stereo_solve_static_ws: an array in the library's code
+// object, so every GPU that loads the library holds its own copy until the
+// process ends.  In host code `scratch` only names the symbol; its device
+// address (one per GPU) is looked up once per device and kept here.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) uint8_t scratch[ZDT_STATIC_WS_BYTES];
+
+namespace {
+// Device address of `scratch` on the GPU that `stream` belongs to (the
+// current GPU for the NULL stream).
+int scratch_for(hipStream_t stream, void** out, const char* who) {
+  int cur = -1, dev = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return fail(ZDT_EHIP, "%s: hipGetDevice failed", who);
+  dev = cur;
+  if (stream && hipStreamGetDevice(stream, &dev) != hipSuccess)
+    return fail(ZDT_EHIP, "%s: hipStreamGetDevice failed", who);
+  if (dev < 0 || dev >= kMaxDevices) return fail(ZDT_EUNSUPPORTED, "%s: device %d", who, dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    if (dev != cur && hipSetDevice(dev) != hipSuccess) return fail(ZDT_EHIP, "%s: hipSetDevice(%d) failed", who, dev);
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (dev != cur) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr)
+      return fail(ZDT_EHIP, "%s: hipGetSymbolAddress(scratch) on device %d: %s", who, dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return ZDT_OK;
+}
+
 // Plan cache file: one line per shape,
 //   zdt-plan W H D R dtype : h_lanes h_seg v_lanes v_seg  (best_us)
 bool read_cached_plan(const char* path, const zdt_params* p, Plan* out) {
@@ -653,6 +692,25 @@ int stereo_solve(const zdt_params* p, const uint8_t* left, const uint8_t* right,
   const JobPtrs j{left, right, disp, vol, ws};
   if (p->dt_iters == 0) return solve_raw(p, j, (hipStream_t)stream);
   return solve_group(p, &j, 1, (hipStream_t)stream);
+}
+
+int stereo_solve_static_ws(const zdt_params* p, const uint8_t* left, const uint8_t* right, int32_t* disp, void* vol,
+                           void* stream) {
+  int rc = check_params(p, "stereo_solve_static_ws");
+  if (rc) return rc;
+  const size_t need = p->dt_iters > 0 ? ws_layout(p).total : 0;
+  if (need > ZDT_STATIC_WS_BYTES)
+    return fail(ZDT_EUNSUPPORTED, "stereo_solve_static_ws: the parameters need %zu B of workspace, more than the %u B "
+                "the library holds", need, (unsigned)ZDT_STATIC_WS_BYTES);
+  hipStream_t s = (hipStream_t)stream;
+  void* ws = nullptr;
+  if (need && (rc = scratch_for(s, &ws, "stereo_solve_static_ws"))) return rc;
+  if ((rc = check_job(p, left, right, disp, vol, ws, "stereo_solve_static_ws"))) return rc;
+  const JobPtrs j{left, right, disp, vol, ws};
+  g_no_alloc = true;
+  rc = p->dt_iters == 0 ? solve_raw(p, j, s) : solve_group(p, &j, 1, s);
+  g_no_alloc = false;
+  return rc;
 }
 
 int stereo_solve_batch(const zdt_job* jobs, int32_t n, void* stream) {

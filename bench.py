@@ -4,12 +4,17 @@ One step = one stereo_solve of a 1280x384 pair, D = 128, 9x9 ZNCC window, DT
 with sigma_s = 20, sigma_r = 0.1 and 3 sweeps, WTA -- the cost, all twelve DT
 passes and the WTA, on inputs already resident in HBM.  The headline value is
 FP32-volume throughput in G cost evaluations per second (W*H*D per step); the
-same line carries the FP16 and BF16 forms, the unfused FP32 per-pair form, the
-roofline of the dominant kernel, the CPU oracle timed on a bounded sample, a
-48-pair mixed-shape batch (FP16, autotuned plans) and the continuous-batching
-server under Poisson arrivals (p50 / p99 latency, with every served result
-checked against the same pair solved alone), and the paper's system S1 (ZNCC
-costs into four-path SGM, then WTA) as one more form.
+same line carries the FP16 and BF16 forms (each with its fraction of the
+B_ref byte model at 8 TB/s), the unfused FP32 per-pair form, the roofline of
+the dominant kernel (its volume nearly fits the 256 MB MALL, so it is labelled
+cache-assisted) and the same at 1920x1080, D = 256, whose volumes are 4-8x the
+MALL, the measured device-copy bandwidth, the CPU oracle timed on a bounded
+sample (all host threads and one core) with the accuracy of every form
+against it at full size, a 48-pair mixed-shape batch (FP16, autotuned plans),
+the continuous-batching server under Poisson arrivals (p50 / p99 latency,
+with every served result checked against the same pair solved alone), and
+the paper's system S1 (ZNCC costs into four-path SGM, then WTA) as one more
+form.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -41,9 +46,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(kernel, s):
-    """Compulsory HBM bytes of one launch at this workload (s = bytes per volume element)."""
-    nvol, npix = W * H * D, W * H
+def algorithmic_bytes(kernel, s, w=W, h=H, d=D):
+    """Compulsory HBM bytes of one launch (s = bytes per volume element)."""
+    nvol, npix = w * h * d, w * h
     return {
         "zncc_hpair": nvol * s + 2 * npix,             # write the volume; read both images
         "zncc_cost": nvol * s + 2 * npix,
@@ -57,10 +62,17 @@ def algorithmic_bytes(kernel, s):
     }.get(kernel)
 
 
-def measured_traffic(kernel, vol_dtype):
+def b_ref(s, iters, w=W, h=H, d=D):
+    """The byte model of the whole path: the volume crosses memory 4 I - 2 times
+    (cost fused into the first H pair, WTA into the last V pair), plus the two
+    images read and the disparities written."""
+    return w * h * d * s * (4 * iters - 2) + 6 * w * h
+
+
+def measured_traffic(kernel, vol_dtype, shape=""):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, vol_dtype))
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s%s.json" % (kernel, vol_dtype, shape))
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -92,20 +104,157 @@ def time_steps(fn, steps, warmup, torch):
     return s.elapsed_time(e) / steps
 
 
-def cpu_baseline(left, right, n_slices, threads):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(left, right, threads, one_core_slices):
+    """The oracle (FP64, single-threaded per call) on the benchmark pair: all
+    128 disparity slices (cost + 3-sweep DT each) over `threads` threads, and
+    `one_core_slices` slices on one thread.  Returns the record and the
+    aggregated volume [H][W][D] of the all-slice run."""
+    import numpy as np
+
     import oracle
-    ds = list(range(0, D, max(1, D // n_slices)))[:n_slices]
     t0 = time.perf_counter()
-    oracle.solve_slices(left, right, R, ds, SIGMA_S, SIGMA_R, ITERS, threads=threads)
+    c = oracle.solve_slices(left, right, R, range(D), SIGMA_S, SIGMA_R, ITERS, threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": round(W * H * len(ds) / dt / 1e9, 6), "unit": "Gcost-evals/s", "cores": threads,
-            "kind": "oracle",
-            "sample": "%d of %d disparity slices of the 1280x384 pair (cost + 3-sweep DT per slice, FP64), "
-                      "%.1f s wall on %d threads" % (len(ds), D, dt, threads)}
+    ds1 = list(range(0, D, D // one_core_slices))[:one_core_slices]
+    t1 = time.perf_counter()
+    oracle.solve_slices(left, right, R, ds1, SIGMA_S, SIGMA_R, ITERS, threads=1)
+    dt1 = time.perf_counter() - t1
+    rec = {"value": round(W * H * D / dt / 1e9, 6), "unit": "Gcost-evals/s", "cores": threads, "kind": "oracle",
+           "sample": "all %d disparity slices of the 1280x384 pair (cost + 3-sweep DT per slice, FP64), %.2f s "
+                     "wall on %d threads" % (D, dt, threads),
+           "single_core": {"value": round(W * H * len(ds1) / dt1 / 1e9, 6), "unit": "Gcost-evals/s", "cores": 1,
+                           "sample": "%d of %d slices, %.2f s on one thread" % (len(ds1), D, dt1)},
+           "nproc": os.cpu_count(), "cpu_model": cpu_model()}
+    return rec, np.ascontiguousarray(np.moveaxis(c, 0, 2))
+
+
+def accuracy_vs_oracle(torch, zdt, L, Rt, pr, disps, cagg, threads):
+    """Every form against the FP64 oracle at 1280x384, D = 128 (the oracle's
+    own aggregated volume from the CPU-baseline run): disparity mismatch; the
+    raw cost volume's max |d cost| in FP32 / FP16 / BF16 (every element); the
+    canonical gap G = C - min_d C of the aggregated volume relative to max_d C
+    -- FP32 and BF16 from dt_aggregate (divided by its reported scale), FP16
+    from stereo_solve's working volume after its last H pair (decoded with its
+    gain map) against the oracle's first ten passes."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    out = {}
+    o_disp = np.argmin(cagg, axis=2)
+    for name, disp in disps.items():
+        out[name] = {"disp_mismatch_pct": round(100.0 * float((disp.cpu().numpy() != o_disp).mean()), 5)}
+
+    def slices(fn):
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            return np.ascontiguousarray(np.stack(list(ex.map(fn, range(D))), axis=2))
+
+    raw = slices(lambda d: oracle.zncc_cost_slice(pr.left, pr.right, R, d))
+    for name, dt in (("f32", zdt.ZDT_F32), ("f16", zdt.ZDT_F16), ("bf16", zdt.ZDT_BF16)):
+        t = torch.empty((H, W, D), dtype=zdt.torch_dtype(dt), device=L.device)
+        zdt.zncc_cost_volume(zdt.params(W, H, D, R, vol_dtype=dt), L, Rt, t)
+        got = t.float().cpu().numpy().astype(np.float64)
+        out[name]["raw_cost_max_abs_err"] = float("%.4g" % np.abs(got - raw).max())
+        if dt != zdt.ZDT_F16:
+            p = zdt.params(W, H, D, R, SIGMA_S, SIGMA_R, ITERS, vol_dtype=dt)
+            scale = zdt.dt_aggregate(p, L, t)
+            agg = t.float().cpu().numpy().astype(np.float64) / scale
+            gap = np.abs((agg - agg.min(axis=2, keepdims=True)) - (cagg - cagg.min(axis=2, keepdims=True)))
+            out[name]["agg_gap_rel_err"] = float("%.4g" % (gap.max(axis=2) / np.abs(cagg).max(axis=2)).max())
+        del t
+    wh, wv = oracle.dt_weights(pr.left, SIGMA_S, SIGMA_R)
+    ten = slices(lambda d: oracle.dt_passes(raw[:, :, d], wh, wv, 0, 4 * ITERS - 2))
+    s16 = zdt.Solver(zdt.params(W, H, D, R, SIGMA_S, SIGMA_R, ITERS, vol_dtype=zdt.ZDT_F16), device=L.device)
+    s16(L, Rt)
+    torch.cuda.synchronize()
+    gain = s16.ws[:W * H * 4].view(torch.float32).reshape(H, W).cpu().numpy()
+    _, e = np.frexp(gain)
+    got = s16.vol.float().cpu().numpy().astype(np.float64) * np.ldexp(1.0, (e - 1) - 13)[:, :, None]
+    gap = np.abs((got - got.min(axis=2, keepdims=True)) - (ten - ten.min(axis=2, keepdims=True)))
+    out["f16"]["working_volume_gap_rel_err"] = float("%.4g" % (gap.max(axis=2) / np.abs(ten).max(axis=2)).max())
+    return out
 
 
 BATCH = {"640x192_d64": 16, "1280x384_d128": 24, "1920x1080_d256": 8}
 POOLS = {"640x192_d64": 4, "1280x384_d128": 2, "1920x1080_d256": 1}
+
+
+def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=5):
+    """A plain device-to-device copy of `nbytes` (read + write counted)."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    ms = time_steps(lambda: dst.copy_(src), reps, 2, torch)
+    del src, dst
+    torch.cuda.empty_cache()
+    return round(2 * nbytes / (ms * 1e-3) / 1e9, 1)
+
+
+def kernel_times(torch, zdt, fn, steps, warmup, s, shape=(W, H, D)):
+    """Per-kernel HIP-event times (recorded by the library on the launch
+    stream) over `steps` calls of fn, with each kernel's algorithmic GB/s."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    zdt.profile_enable(True)
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    kt = zdt.profile_collect()
+    zdt.profile_enable(False)
+    ks = {k: {"avg_us": round(1e3 * ms / n, 3), "launches": n} for k, (ms, n) in kt.items()}
+    for k in ks:
+        b = algorithmic_bytes(k, s, *shape)
+        if b:
+            ks[k]["GBps"] = round(b / (ks[k]["avg_us"] * 1e-6) / 1e9, 1)
+    return kt, ks
+
+
+def roofline_of(kt, s, dtype_name, shape, traffic_tag, note):
+    """Roofline object of the kernel with the most total time."""
+    dom = max(kt, key=lambda k: kt[k][0])
+    avg_s = kt[dom][0] / kt[dom][1] * 1e-3
+    abytes = algorithmic_bytes(dom, s, *shape)
+    achieved = abytes / avg_s / 1e9
+    return {"bound": "hbm", "kernel": dom, "vol_dtype": dtype_name, "achieved": round(achieved, 1),
+            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": measured_traffic(dom, dtype_name, traffic_tag), "algorithmic_bytes": abytes,
+            "avg_us": round(avg_s * 1e6, 3), "cache": note}
+
+
+def bench_out_of_cache(torch, zdt, dev, steps, warmup):
+    """1920x1080, D = 256 (FP32 volume 2.1 GB, FP16 1.06 GB: 4-8x the MALL):
+    whole solves and the dominant kernel's roofline per volume type."""
+    from paper_2212_00476_amd import scenes
+    w, h, d = 1920, 1080, 256
+    pr = scenes.workload("planes_1920x1080_d256")
+    L = torch.from_numpy(pr.left).to(dev)
+    Rt = torch.from_numpy(pr.right).to(dev)
+    out = {"workload": "planes_1920x1080_d256", "width": w, "height": h, "max_disp": d}
+    for name, dt, s in (("f32", zdt.ZDT_F32, 4), ("f16", zdt.ZDT_F16, 2)):
+        solver = zdt.Solver(zdt.params(w, h, d, R, SIGMA_S, SIGMA_R, ITERS, vol_dtype=dt), device=dev)
+        disp = torch.empty((h, w), dtype=torch.int32, device=dev)
+        fn = lambda: solver(L, Rt, disp)  # noqa: E731
+        ms = time_steps(fn, steps, warmup, torch)
+        kt, ks = kernel_times(torch, zdt, fn, steps, 1, s, (w, h, d))
+        out[name] = {"ms_per_step": round(ms, 4), "gcost_evals_per_s": round(w * h * d / (ms * 1e-3) / 1e9, 3),
+                     "b_ref_frac": round(b_ref(s, ITERS, w, h, d) / (ms * 1e-3) / (PEAK_HBM_GBS * 1e9), 4),
+                     "kernels": ks,
+                     "roofline": roofline_of(kt, s, name, (w, h, d), "_1920x1080",
+                                             "out of cache: the volume is 4-8x the 256 MB MALL")}
+        del solver, disp
+        torch.cuda.empty_cache()
+    return out
 
 
 def bench_batch(torch, zdt, reps=3):
@@ -170,8 +319,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-slices", type=int, default=128)
+    ap.add_argument("--cpu-one-core-slices", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the 1920x1080, D = 256 forms")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for rocprofv3 byte counters)")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="length of the served Poisson run (0: skip)")
@@ -203,29 +353,31 @@ def main():
 
     forms = {}
     solvers = {}
-    for name, dt in (("f32", zdt.ZDT_F32), ("f16", zdt.ZDT_F16), ("bf16", zdt.ZDT_BF16)):
+    for name, dt, sz in (("f32", zdt.ZDT_F32, 4), ("f16", zdt.ZDT_F16, 2), ("bf16", zdt.ZDT_BF16, 2)):
         p = zdt.params(W, H, D, R, SIGMA_S, SIGMA_R, ITERS, vol_dtype=dt)
         solver = zdt.Solver(p, device=dev)
         disp = torch.empty((H, W), dtype=torch.int32, device=dev)
         solvers[name] = (solver, disp)
         ms = time_steps(lambda: solver(L, Rt, disp), args.steps, args.warmup, torch)
         forms[name] = {"ms_per_step": round(ms, 5), "gcost_evals_per_s": round(nvol / (ms * 1e-3) / 1e9, 3),
-                       "fps": round(1000.0 / ms, 1), "d1_error_pct": d1_error_pct(disp, pr)}
+                       "fps": round(1000.0 / ms, 1), "d1_error_pct": d1_error_pct(disp, pr),
+                       "b_ref_frac": round(b_ref(sz, ITERS) / (ms * 1e-3) / (PEAK_HBM_GBS * 1e9), 4)}
 
     # the paper's own system parameters: 3x3 window, one sweep, sigma_s = 5,
     # sigma_r = 52 on 0..255 (the configuration of its 32 fps Jetson TX2 figure)
     # (plus its Int16 / Int8 narrow volumes, T = 21, d_arb = 0; their
     # disparities are compared with this FP32 form's)
     paper_ref = None
-    for name, dt in (("paper_cfg_f32", zdt.ZDT_F32), ("paper_cfg_f16", zdt.ZDT_F16), ("paper_cfg_i16", zdt.ZDT_I16),
-                     ("paper_cfg_i8", zdt.ZDT_I8)):
+    for name, dt, sz in (("paper_cfg_f32", zdt.ZDT_F32, 4), ("paper_cfg_f16", zdt.ZDT_F16, 2),
+                         ("paper_cfg_i16", zdt.ZDT_I16, 2), ("paper_cfg_i8", zdt.ZDT_I8, 1)):
         p = zdt.params(W, H, D, 1, 5.0, 52.0 / 255.0, 1, vol_dtype=dt)
         solver = zdt.Solver(p, device=dev)
         disp = torch.empty((H, W), dtype=torch.int32, device=dev)
         ms = time_steps(lambda: solver(L, Rt, disp), args.steps, args.warmup, torch)
         forms[name] = {"ms_per_step": round(ms, 5), "gcost_evals_per_s": round(nvol / (ms * 1e-3) / 1e9, 3),
                        "fps": round(1000.0 / ms, 1), "window": 3, "dt_iters": 1, "sigma_s": 5.0,
-                       "sigma_r": round(52.0 / 255.0, 6), "d1_error_pct": d1_error_pct(disp, pr)}
+                       "sigma_r": round(52.0 / 255.0, 6), "d1_error_pct": d1_error_pct(disp, pr),
+                       "b_ref_frac": round(b_ref(sz, 1) / (ms * 1e-3) / (PEAK_HBM_GBS * 1e9), 4)}
         if paper_ref is None:
             paper_ref = disp.clone()
         else:
@@ -290,49 +442,33 @@ def main():
         else:
             forms[name]["disagreement_vs_f32"] = round(float((disp_s1 != s1_ref).float().mean()), 6)
 
-    # per-kernel HIP-event times (recorded on the launch stream) over timed steps
-    def kernel_times(fn, s):
-        for _ in range(args.warmup):
-            fn()
-        torch.cuda.synchronize()
-        zdt.profile_enable(True)
-        for _ in range(args.steps):
-            fn()
-        torch.cuda.synchronize()
-        kt = zdt.profile_collect()
-        zdt.profile_enable(False)
-        ks = {k: {"avg_us": round(1e3 * ms / n, 3), "launches": n} for k, (ms, n) in kt.items()}
-        for k in ks:
-            b = algorithmic_bytes(k, s)
-            if b:
-                ks[k]["GBps"] = round(b / (ks[k]["avg_us"] * 1e-6) / 1e9, 1)
-        return kt, ks
-
     def solve_fn(name):
         solver, disp = solvers[name]
         return lambda: solver(L, Rt, disp)
 
-    kt, kernels = kernel_times(solve_fn("f32"), 4)
-    kernels_f16 = kernel_times(solve_fn("f16"), 2)[1]
-    kernels_bf16 = kernel_times(solve_fn("bf16"), 2)[1]
-    kernels_sgm = kernel_times(s1_fns["sgm_s1_f32"], 4)[1]
-    kernels_sgm_f16 = kernel_times(s1_fns["sgm_s1_f16"], 2)[1]
-    dom = max(kt, key=lambda k: kt[k][0])
-    avg_s = kt[dom][0] / kt[dom][1] * 1e-3
-    abytes = algorithmic_bytes(dom, 4)
-    achieved = abytes / avg_s / 1e9
-    traffic = measured_traffic(dom, "f32")
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                "algorithmic_bytes": abytes, "avg_us": round(avg_s * 1e6, 3)}
+    def ktimes(fn, s):
+        return kernel_times(torch, zdt, fn, args.steps, args.warmup, s)
+
+    mall = "cache-assisted: the 252 MB FP32 volume is about the 256 MB MALL (the FP16 one fits in it)"
+    kt, kernels = ktimes(solve_fn("f32"), 4)
+    kt16, kernels_f16 = ktimes(solve_fn("f16"), 2)
+    kernels_bf16 = ktimes(solve_fn("bf16"), 2)[1]
+    kernels_sgm = ktimes(s1_fns["sgm_s1_f32"], 4)[1]
+    kernels_sgm_f16 = ktimes(s1_fns["sgm_s1_f16"], 2)[1]
+    roofline = roofline_of(kt, 4, "f32", (W, H, D), "", mall)
+    roofline_f16 = roofline_of(kt16, 2, "f16", (W, H, D), "", mall)
+    copy_gbs = copy_bandwidth(torch, dev)
+    large = None if args.no_large else bench_out_of_cache(torch, zdt, dev, max(5, args.steps // 20), 2)
 
     batch = None if args.no_batch else bench_batch(torch, zdt)
     served = bench_serving(torch, zdt, args.serve_seconds) if args.serve_seconds > 0 else None
 
-    cpu = None
+    cpu = accuracy = None
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)
-        cpu = cpu_baseline(pr.left, pr.right, args.cpu_slices, threads)
+        cpu, cagg = cpu_baseline(pr.left, pr.right, threads, args.cpu_one_core_slices)
+        accuracy = accuracy_vs_oracle(torch, zdt, L, Rt, pr, {k: v[1] for k, v in solvers.items()}, cagg, threads)
+        del cagg
 
     f32 = forms["f32"]
     line = {
@@ -344,7 +480,8 @@ def main():
                    "parallelism": "single-gpu"},
         "fps": f32["fps"], "forms": forms, "kernels_f32": kernels, "kernels_f16": kernels_f16,
         "kernels_bf16": kernels_bf16, "kernels_sgm_s1": kernels_sgm,
-        "kernels_sgm_s1_f16": kernels_sgm_f16, "roofline": roofline, "cpu_baseline": cpu,
+        "kernels_sgm_s1_f16": kernels_sgm_f16, "roofline": roofline, "roofline_f16": roofline_f16,
+        "copy_GBps": copy_gbs, "out_of_cache": large, "cpu_baseline": cpu, "accuracy_vs_oracle": accuracy,
         "p99_ms_served": served["poisson"]["p99_ms"] if served else None,
         "batch": batch, "serving": served,
         "window_sweep_cost_ms": sweep,

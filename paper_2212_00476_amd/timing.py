@@ -24,6 +24,8 @@ def main(argv=None):
     ap.add_argument("--radius", type=int, default=4)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 256 MiB device copy three times (reference for byte counters)")
     args = ap.parse_args(argv)
 
     import torch
@@ -36,6 +38,13 @@ def main(argv=None):
     H, W = pr.left.shape
     D = int(args.workload.rsplit("_d", 1)[1])
     left, right = torch.from_numpy(pr.left).cuda(), torch.from_numpy(pr.right).cuda()
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for name in args.dtype or ["f32"]:
         solver = Solver(params(W, H, D, args.radius, vol_dtype=codes[name]))
         for _ in range(args.warmup):

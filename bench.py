@@ -288,30 +288,42 @@ def bench_batch(torch, zdt, reps=3):
             "plans": plans}
 
 
-def bench_serving(torch, zdt, seconds):
-    """Poisson arrivals at 300 pairs/s of the three-shape mix through the
-    continuous-batching server (FP16 volumes, graphs), every result checked
-    against the pair solved alone; then the server's capacity (all requests
-    offered at 3000/s) next to plain FP32 per-pair solves of the same requests."""
+def bench_serving(torch, zdt, seconds, pairs_per_shape):
+    """Config 4: Poisson arrivals at 300 pairs/s for `seconds` of the
+    three-shape mix (50 / 40 / 10 %), each request one of `pairs_per_shape`
+    seeded pairs of its shape (generated before the clock starts), through the
+    continuous-batching server (FP16 volumes, lanes opened on demand under a
+    64 GB HBM budget, library-captured graphs), every result checked against
+    the pair solved alone; then the server's capacity (requests offered at
+    3000/s for 1 s) next to plain FP32 per-pair solves of the same requests."""
     from paper_2212_00476_amd import serving
-    pools = serving.make_pairs(POOLS)
+    workers = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    pools = serving.make_pairs({s.name: pairs_per_shape for s in serving.SHAPES}, workers=workers)
+    gen_s = time.perf_counter() - t0
     npairs = {k: len(v) for k, v in pools.items()}
-    ex = serving.GpuExecutor(pools, vol_dtype=zdt.ZDT_F16, lanes=2)
-    reqs = serving.poisson_arrivals(300.0, seconds, serving.MIX, npairs, seed=5)
-    serving.serve(reqs, ex.scheduler(), ex)
+    ex = serving.GpuExecutor(pools, vol_dtype=zdt.ZDT_F16, budget_bytes=64 * 10 ** 9)
+    sched = ex.scheduler()
+    reqs = serving.poisson_arrivals(300.0, seconds, serving.MIX, npairs, seed=7)
+
+    def progress(t, done):
+        print("serving: %.0f s, %d of %d requests done" % (t, done, len(reqs)), file=sys.stderr, flush=True)
+    serving.serve(reqs, sched, ex, progress=progress)
     poisson = serving.summarize(reqs, duration=seconds)
-    poisson.update({"offered_per_s": 300.0, "seconds": seconds})
+    poisson.update({"offered_per_s": 300.0, "seconds": seconds, "pairs_per_shape": pairs_per_shape,
+                    "pool_generation_s": round(gen_s, 1), "budget_gb": round(ex.budget / 1e9, 1),
+                    "peak_lane_gb": round(sched.peak / 1e9, 3), "lanes_opened": dict(sched._next),
+                    "waited_for_memory": len(sched.waited_for_memory), "graph_captures": ex.graph_captures})
     burst = serving.poisson_arrivals(3000.0, 1.0, serving.MIX, npairs, seed=6)
-    serving.serve(burst, ex.scheduler(), ex)
+    serving.serve(burst, sched, ex)
     cap = serving.summarize(burst)
-    served_cap = cap["pairs_per_s"]
-    vol_gb = round(ex.volume_bytes / 1e9, 2)
-    del ex
+    sched.close()
+    del ex, sched
     torch.cuda.empty_cache()
     per_pair = serving.per_pair_capacity(burst, pools, zdt.ZDT_F32)
-    return {"poisson": poisson, "capacity_f16_served_pairs_per_s": served_cap,
+    return {"poisson": poisson, "capacity_f16_served_pairs_per_s": cap["pairs_per_s"],
             "capacity_f32_per_pair_pairs_per_s": round(per_pair, 1), "capacity_requests": len(burst),
-            "capacity_mismatched": cap["mismatched"], "lane_volumes_gb": vol_gb}
+            "capacity_mismatched": cap["mismatched"]}
 
 
 def main():
@@ -324,7 +336,8 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 1920x1080, D = 256 forms")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for rocprofv3 byte counters)")
-    ap.add_argument("--serve-seconds", type=float, default=10.0, help="length of the served Poisson run (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="length of the served Poisson run (0: skip)")
+    ap.add_argument("--serve-pairs", type=int, default=64, help="seeded pairs per shape the requests draw from")
     ap.add_argument("--no-batch", action="store_true", help="skip the 48-pair batch")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -461,7 +474,7 @@ def main():
     large = None if args.no_large else bench_out_of_cache(torch, zdt, dev, max(5, args.steps // 20), 2)
 
     batch = None if args.no_batch else bench_batch(torch, zdt)
-    served = bench_serving(torch, zdt, args.serve_seconds) if args.serve_seconds > 0 else None
+    served = bench_serving(torch, zdt, args.serve_seconds, args.serve_pairs) if args.serve_seconds > 0 else None
 
     cpu = accuracy = None
     if not args.no_cpu:

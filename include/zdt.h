@@ -162,6 +162,22 @@ typedef struct zdt_job {
  * job i's error is reported with its index.  n = 0 does nothing. */
 int stereo_solve_batch(const zdt_job* jobs, int32_t n, void* stream);
 
+/* Graphs of a batch (serving loops): stereo_solve_batch(jobs, n) recorded
+ * once on `stream` (hipStreamBeginCapture, thread-local mode) into an
+ * executable HIP graph (hipGraphInstantiate) that zdt_graph_launch() replays
+ * on any stream.  The jobs' device buffers and parameters are baked into the
+ * graph: a replay solves whatever the images hold at that time, into the same
+ * disparity buffers, so callers refill the images between replays (and order
+ * replays that share buffers).  zdt_graph_create() first runs the batch once,
+ * eagerly, on `stream` (which must not be the NULL stream) so that the capture
+ * records launches only; the captured kernels include no memset.  The graph
+ * object is owned by the caller (zdt_graph_destroy).  Same errors as
+ * stereo_solve_batch(), ZDT_EHIP when capture or instantiation fails. */
+typedef struct zdt_graph zdt_graph;
+int zdt_graph_create(const zdt_job* jobs, int32_t n, void* stream, zdt_graph** out);
+int zdt_graph_launch(zdt_graph* graph, void* stream);
+int zdt_graph_destroy(zdt_graph* graph);
+
 /* Semi-global matching over a cost volume: the aggregation of the paper's
  * system S1 (Sec. V-D, Table IV), where ZNCC costs multiplied by T feed SGM
  * with P1 = 18, P2 = 185.  The paper takes SGM from its reference [r7]; this

@@ -12,6 +12,7 @@ the tests and the benchmark.  PyTorch provides device memory and streams only.
 from __future__ import annotations
 
 from ._lib import (ZDT_BF16, ZDT_F16, ZDT_F32, ZDT_FLAG_GUIDE_TARGET, ZDT_FLAG_NORMALIZE, ZDT_I8, ZDT_I16, ZdtError,
+                   Graph,
                    ZdtParams, autotune, dt_aggregate, get_plan, i8_codec, load, params, plan_candidates,
                    profile_collect, profile_enable,
                    set_plan, sgm_aggregate, sgm_disparity, stereo_solve, stereo_solve_batch, stereo_solve_sgm,
@@ -20,7 +21,7 @@ from ._lib import (ZDT_BF16, ZDT_F16, ZDT_F32, ZDT_FLAG_GUIDE_TARGET, ZDT_FLAG_N
                    zncc_cost_volume, zncc_window_sums, zncc_window_sums_integral, integral_workspace_size)
 
 __all__ = ["ZDT_F32", "ZDT_F16", "ZDT_BF16", "ZDT_I16", "ZDT_I8", "ZDT_FLAG_NORMALIZE", "ZDT_FLAG_GUIDE_TARGET",
-           "ZdtError", "ZdtParams", "i8_codec",
+           "ZdtError", "ZdtParams", "Graph", "i8_codec",
            "params", "load", "zncc_cost_volume", "dt_aggregate", "wta_disparity", "stereo_solve",
            "stereo_solve_static_ws", "STATIC_WS_BYTES",
            "stereo_solve_batch", "sgm_aggregate", "sgm_disparity", "stereo_solve_sgm",

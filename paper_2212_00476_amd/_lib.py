@@ -19,7 +19,8 @@ ZDT_FLAG_NORMALIZE = 1
 ZDT_FLAG_GUIDE_TARGET = 2
 
 EXPORTED = ("zdt_workspace_size", "zdt_volume_size", "zncc_cost_volume", "dt_aggregate", "wta_disparity",
-            "stereo_solve", "stereo_solve_static_ws", "stereo_solve_batch", "zdt_plan_candidates", "zdt_get_plan", "zdt_set_plan",
+            "stereo_solve", "stereo_solve_static_ws", "stereo_solve_batch", "zdt_graph_create",
+            "zdt_graph_launch", "zdt_graph_destroy", "zdt_plan_candidates", "zdt_get_plan", "zdt_set_plan",
             "zdt_autotune", "zncc_window_sums", "zdt_i8_codec", "sgm_aggregate", "sgm_disparity",
             "stereo_solve_sgm", "zdt_integral_workspace_size", "zncc_window_sums_integral", "zdt_last_error", "zdt_profile_enable", "zdt_profile_collect", "zdt_profile_entry")
 
@@ -73,6 +74,9 @@ def load():
     lib.stereo_solve_static_ws.argtypes = [PP, P, P, P, P, P]
     lib.zncc_window_sums.argtypes = [PP, P, P, P, P, P, P, P, P]
     lib.stereo_solve_batch.argtypes = [ctypes.POINTER(ZdtJob), ctypes.c_int32, P]
+    lib.zdt_graph_create.argtypes = [ctypes.POINTER(ZdtJob), ctypes.c_int32, P, ctypes.POINTER(ctypes.c_void_p)]
+    lib.zdt_graph_launch.argtypes = [P, P]
+    lib.zdt_graph_destroy.argtypes = [P]
     PL = ctypes.POINTER(ZdtPlan)
     lib.zdt_plan_candidates.argtypes = [PP, PL, ctypes.c_int]
     lib.zdt_get_plan.argtypes = [PP, PL]
@@ -91,7 +95,7 @@ def load():
     lib.zdt_profile_entry.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     for f in ("zncc_cost_volume", "dt_aggregate", "wta_disparity", "stereo_solve", "stereo_solve_static_ws",
-              "stereo_solve_batch",
+              "stereo_solve_batch", "zdt_graph_create", "zdt_graph_launch", "zdt_graph_destroy",
               "zdt_plan_candidates", "zdt_get_plan", "zdt_set_plan", "zdt_autotune", "zncc_window_sums", "zdt_i8_codec",
               "sgm_aggregate", "sgm_disparity", "stereo_solve_sgm", "zncc_window_sums_integral", "zdt_profile_enable",
               "zdt_profile_collect",
@@ -167,6 +171,40 @@ def stereo_solve_batch(jobs, stream=None):
     for i, (p, left, right, disp, vol, ws) in enumerate(jobs):
         arr[i] = ZdtJob(p, _ptr(left), _ptr(right), _ptr(disp), _ptr(vol), _ptr(ws))
     _check("stereo_solve_batch", load().stereo_solve_batch(arr, len(jobs), _stream(stream)))
+
+
+def _job_array(jobs):
+    arr = (ZdtJob * len(jobs))()
+    for i, (p, left, right, disp, vol, ws) in enumerate(jobs):
+        arr[i] = ZdtJob(p, _ptr(left), _ptr(right), _ptr(disp), _ptr(vol), _ptr(ws))
+    return arr
+
+
+class Graph:
+    """stereo_solve_batch(jobs) captured by the library into a HIP graph
+    (zdt_graph_create); launch() replays it on a stream.  The jobs' tensors
+    must stay alive as long as the graph."""
+
+    def __init__(self, jobs, stream):
+        self._jobs = list(jobs)
+        h = ctypes.c_void_p()
+        _check("zdt_graph_create", load().zdt_graph_create(_job_array(self._jobs), len(self._jobs),
+                                                            _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check("zdt_graph_launch", load().zdt_graph_launch(self._h, _stream(stream)))
+
+    def close(self):
+        if self._h:
+            _check("zdt_graph_destroy", load().zdt_graph_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def plan_candidates(p):

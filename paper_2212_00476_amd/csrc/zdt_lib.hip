@@ -12,6 +12,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <new>
 #include <tuple>
 #include <string>
 #include <unordered_map>
@@ -803,6 +804,63 @@ int stereo_solve_sgm(const zdt_params* p, const uint8_t* left, const uint8_t* ri
   if (!left || !right || !disp) return fail(ZDT_EINVAL, "stereo_solve_sgm: NULL image or disparity pointer");
   if ((rc = zncc_cost_volume(p, left, right, cost, stream))) return rc;
   return sgm_disparity(p, cost, sum, disp, p1, p2, cost_scale, stream);
+}
+
+// ---- graphs: stereo_solve_batch captured once, replayed many times
+}  // extern "C"
+struct zdt_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+extern "C" {
+
+int zdt_graph_create(const zdt_job* jobs, int32_t n, void* stream, zdt_graph** out) {
+  if (!out) return fail(ZDT_EINVAL, "zdt_graph_create: NULL output");
+  *out = nullptr;
+  if (n < 1 || !jobs) return fail(ZDT_EINVAL, "zdt_graph_create: %d jobs at %p", n, (const void*)jobs);
+  hipStream_t s = (hipStream_t)stream;
+  if (!s) return fail(ZDT_EINVAL, "zdt_graph_create: capture needs a stream other than the NULL stream");
+  // A first, eager run prepares every kernel (attribute queries, LDS limits)
+  // so that the capture itself only records launches.
+  int rc = stereo_solve_batch(jobs, n, stream);
+  if (rc) return rc;
+  zdt_graph* g = new (std::nothrow) zdt_graph();
+  if (!g) return fail(ZDT_ENOMEM, "zdt_graph_create: out of host memory");
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    delete g;
+    return fail(ZDT_EHIP, "zdt_graph_create: hipStreamBeginCapture: %s", hipGetErrorString(e));
+  }
+  g_no_alloc = true;  // no timing events inside the graph
+  rc = stereo_solve_batch(jobs, n, stream);
+  g_no_alloc = false;
+  e = hipStreamEndCapture(s, &g->graph);
+  if (rc == ZDT_OK && e != hipSuccess) rc = fail(ZDT_EHIP, "zdt_graph_create: hipStreamEndCapture: %s", hipGetErrorString(e));
+  if (rc == ZDT_OK && (e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0)) != hipSuccess)
+    rc = fail(ZDT_EHIP, "zdt_graph_create: hipGraphInstantiate: %s", hipGetErrorString(e));
+  if (rc) {
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return rc;
+  }
+  *out = g;
+  return ZDT_OK;
+}
+
+int zdt_graph_launch(zdt_graph* g, void* stream) {
+  if (!g || !g->exec) return fail(ZDT_EINVAL, "zdt_graph_launch: NULL graph");
+  const hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(ZDT_EHIP, "zdt_graph_launch: %s", hipGetErrorString(e));
+  return ZDT_OK;
+}
+
+int zdt_graph_destroy(zdt_graph* g) {
+  if (!g) return ZDT_OK;
+  int rc = ZDT_OK;
+  if (g->exec && hipGraphExecDestroy(g->exec) != hipSuccess) rc = fail(ZDT_EHIP, "zdt_graph_destroy: exec");
+  if (g->graph && hipGraphDestroy(g->graph) != hipSuccess) rc = fail(ZDT_EHIP, "zdt_graph_destroy: graph");
+  delete g;
+  return rc;
 }
 
 int zdt_plan_candidates(const zdt_params* p, zdt_plan* out, int max) {

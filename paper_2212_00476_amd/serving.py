@@ -1,24 +1,32 @@
 """Continuous-batching stereo server on one GPU.
 
-Requests (a stereo pair of one of several shapes) arrive over time; each shape
-has a few execution lanes, every lane with its own HIP stream, its own
-device-resident inputs, working volumes, workspaces and disparity buffers for
-up to `max_batch` pairs, and one captured HIP graph per batch size.  Whenever a
-lane is free and pairs of its shape are waiting, the lane takes up to
-`max_batch` of them (oldest first): their images are copied into the lane's
-slots, the graph for that batch size is replayed (one launch per stage over
-all of them, see ``stereo_solve_batch``) and the disparities are copied back
-to pinned host memory.  Pairs that arrive while others run are admitted as soon
-as a lane of their shape frees up, and lanes of different shapes (and of the
-same shape) overlap on the device.  The lanes' volumes are allocated once, up
-front, and must fit the HBM budget for live cost volumes.
+Requests (a stereo pair of any size and disparity range) arrive over time.
+Pairs of one shape (W, H, D) are served by *lanes*: a lane owns a HIP stream,
+device buffers for up to B pairs of its shape (images, working volume,
+workspace, disparities) and pinned host memory for the results, and replays a
+library-captured HIP graph per batch size (``zdt_graph_create``).  Whenever a
+lane is free and pairs of its shape wait, it takes up to B of them (oldest
+first): their images are copied into its slots, the graph for that batch size
+is replayed (one launch per stage over all of them, see
+``stereo_solve_batch``) and the disparities are copied back.  Pairs that arrive
+while others run are admitted as soon as a lane frees up, and lanes of
+different shapes (and of the same shape) overlap on the device.
+
+Admission is by an HBM budget for live buffers (64 GB by default): a lane is
+created on demand -- for a shape seen for the first time, or when every lane
+of a busy shape is taken -- only if its bytes (B pairs' volumes, workspaces,
+images and disparities) fit in what the budget has left.  Otherwise idle lanes
+of other shapes are released, least recently used first; if that is not
+enough, the request waits until memory frees, and while the oldest waiting
+request waits for memory no new lane is opened for a younger one.  A shape's
+graphs are captured on its lanes' first batches of each size.
 
 The paper solves one pair at a time without streams; this module is the
 serving layer around its hot path.  The scheduler is plain host logic
 (``Scheduler``, ``serve``) driven by an executor; ``GpuExecutor`` runs it on
 the device and can check every result against the same pair solved alone.
 
-    python -m paper_2212_00476_amd.serving --rate 300 --duration 10
+    python -m paper_2212_00476_amd.serving --rate 300 --duration 60
 """
 from __future__ import annotations
 
@@ -40,8 +48,14 @@ class Shape:
     D: int
 
 
-SHAPES = (Shape("640x192_d64", 640, 192, 64), Shape("1280x384_d128", 1280, 384, 128),
-          Shape("1920x1080_d256", 1920, 1080, 256))
+def shape_of(name):
+    """Shape named "<W>x<H>_d<D>"."""
+    wh, d = name.split("_d")
+    w, h = wh.split("x")
+    return Shape(name, int(w), int(h), int(d))
+
+
+SHAPES = (shape_of("640x192_d64"), shape_of("1280x384_d128"), shape_of("1920x1080_d256"))
 MIX = {"640x192_d64": 0.5, "1280x384_d128": 0.4, "1920x1080_d256": 0.1}
 
 
@@ -78,35 +92,111 @@ def poisson_arrivals(rate, duration, mix=MIX, pairs_per_shape=None, seed=0):
         out.append(Request(len(out), name, int(r_p.uniform() * npairs), t))
 
 
-class Scheduler:
-    """Per-shape FIFO queues and execution lanes.  A lane is (shape, k)."""
+@dataclass
+class _LaneState:
+    shape: str
+    capacity: int      # pairs per batch
+    nbytes: int
+    busy: bool = False
+    last_used: int = 0
 
-    def __init__(self, lanes, max_batch):
-        self.max_batch = dict(max_batch)
-        self.queues = {s: deque() for s in lanes}
-        self.free = {s: deque((s, k) for k in range(n)) for s, n in lanes.items()}
+
+class Scheduler:
+    """Per-shape FIFO queues; lanes opened and released against an HBM budget.
+
+    `executor` provides lane_plan(shape) -> (capacity, bytes), and
+    create_lane(lane, shape, capacity) / destroy_lane(lane).  A lane id is
+    (shape, k)."""
+
+    def __init__(self, executor, budget_bytes, max_lanes_per_shape=4):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.max_lanes = max_lanes_per_shape
+        self.queues = {}
+        self.lanes = {}
         self.running = {}
+        self.used = 0
+        self.peak = 0
+        self.waited_for_memory = set()   # ids of requests that had to wait for memory
+        self.released = 0                # idle lanes released to make room
+        self._tick = 0
+        self._next = {}
 
     def arrive(self, req):
-        self.queues[req.shape].append(req)
+        _, nbytes = self.ex.lane_plan(req.shape)
+        if nbytes > self.budget:
+            raise ValueError("a lane of %s needs %.2f GB, more than the whole %.2f GB budget"
+                             % (req.shape, nbytes / 1e9, self.budget / 1e9))
+        self.queues.setdefault(req.shape, deque()).append(req)
+
+    def _idle_lane(self, shape):
+        best = None
+        for lane, st in self.lanes.items():
+            if st.shape == shape and not st.busy and (best is None or st.last_used > self.lanes[best].last_used):
+                best = lane
+        return best
+
+    def _release_for(self, nbytes, keep_shape):
+        """Release idle lanes of other shapes, least recently used first, until
+        `nbytes` fit; True if they do."""
+        idle = sorted((st.last_used, lane) for lane, st in self.lanes.items()
+                      if not st.busy and st.shape != keep_shape)
+        for _, lane in idle:
+            if self.used + nbytes <= self.budget:
+                break
+            self.ex.destroy_lane(lane)
+            self.used -= self.lanes.pop(lane).nbytes
+            self.released += 1
+        return self.used + nbytes <= self.budget
+
+    def _open_lane(self, shape):
+        """(new lane, None), or (None, "lanes") when the shape has its maximum
+        of lanes, or (None, "memory") when the budget cannot take one more."""
+        cap, nbytes = self.ex.lane_plan(shape)
+        if sum(st.shape == shape for st in self.lanes.values()) >= self.max_lanes:
+            return None, "lanes"
+        if self.used + nbytes > self.budget and not self._release_for(nbytes, shape):
+            return None, "memory"
+        k = self._next.get(shape, 0)
+        self._next[shape] = k + 1
+        lane = (shape, k)
+        self.ex.create_lane(lane, shape, cap)
+        self.lanes[lane] = _LaneState(shape, cap, nbytes)
+        self.used += nbytes
+        self.peak = max(self.peak, self.used)
+        return lane, None
 
     def dispatch(self):
-        """[(lane, batch)] for every free lane whose shape has waiting requests;
-        shapes whose oldest request waited longest go first."""
+        """[(lane, batch)] to launch now: shapes whose oldest request waited
+        longest go first; each takes idle lanes of its shape, then new lanes
+        while the budget allows.  Once a request waits for memory, younger
+        shapes only reuse the lanes they have."""
         out = []
+        blocked = False
         order = sorted((q[0].t_arrive, s) for s, q in self.queues.items() if q)
         for _, s in order:
-            q, free = self.queues[s], self.free[s]
-            while q and free:
-                lane = free.popleft()
-                batch = [q.popleft() for _ in range(min(len(q), self.max_batch[s]))]
+            q = self.queues[s]
+            while q:
+                lane = self._idle_lane(s)
+                if lane is None and not blocked:
+                    lane, why = self._open_lane(s)
+                    if why == "memory":
+                        blocked = True
+                        self.waited_for_memory.add(q[0].rid)
+                if lane is None:
+                    break
+                st = self.lanes[lane]
+                batch = [q.popleft() for _ in range(min(len(q), st.capacity))]
+                st.busy = True
+                self._tick += 1
+                st.last_used = self._tick
                 self.running[lane] = batch
                 out.append((lane, batch))
         return out
 
     def complete(self, lane):
         batch = self.running.pop(lane)
-        self.free[lane[0]].append(lane)
+        self.lanes[lane].busy = False
         return batch
 
     def busy_lanes(self):
@@ -118,13 +208,21 @@ class Scheduler:
     def idle(self):
         return not self.running and self.waiting() == 0
 
+    def close(self):
+        for lane in list(self.lanes):
+            if not self.lanes[lane].busy:
+                self.ex.destroy_lane(lane)
+                self.used -= self.lanes.pop(lane).nbytes
 
-def serve(requests, scheduler, executor, clock=time.perf_counter, sleep=time.sleep):
+
+def serve(requests, scheduler, executor, clock=time.perf_counter, sleep=time.sleep, progress=None):
     """Run the requests in real time (request i arrives t_arrive seconds after
-    the start) and return them with t_start / t_done filled in."""
+    the start) and return them with t_start / t_done filled in.  `progress`,
+    if given, is called about every 10 s of the run with (seconds, done)."""
     reqs = sorted(requests, key=lambda r: r.t_arrive)
     t0 = clock()
-    i = 0
+    i = done = 0
+    next_note = 10.0
     while i < len(reqs) or not scheduler.idle():
         now = clock() - t0
         while i < len(reqs) and reqs[i].t_arrive <= now:
@@ -137,6 +235,7 @@ def serve(requests, scheduler, executor, clock=time.perf_counter, sleep=time.sle
                 batch = scheduler.complete(lane)
                 for r in batch:
                     r.t_done = t
+                done += len(batch)
                 executor.finish(lane, batch)
                 progressed = True
         for lane, batch in scheduler.dispatch():
@@ -145,6 +244,9 @@ def serve(requests, scheduler, executor, clock=time.perf_counter, sleep=time.sle
                 r.t_start = t
             executor.launch(lane, batch)
             progressed = True
+        if progress and now >= next_note:
+            progress(now, done)
+            next_note += 10.0
         if not progressed:
             nxt = reqs[i].t_arrive - (clock() - t0) if i < len(reqs) else 0.0
             sleep(min(max(nxt, 0.0), 2e-4) if scheduler.busy_lanes() or nxt > 0 else 0.0)
@@ -181,86 +283,94 @@ class _Lane:
     jobs: list
     event: object
     graphs: dict = field(default_factory=dict)
-    batch: list = field(default_factory=list)
 
 
 class GpuExecutor:
-    """Lanes on the device: buffers allocated once, one captured graph per
-    (lane, batch size), a completion event per launch.
+    """Lanes on the device, opened and released by the scheduler.
 
-    pairs: {shape name: [StereoPair, ...]} -- the inputs requests refer to.
+    pairs: {shape name: [StereoPair, ...]} -- the inputs requests refer to;
+      shape names are "<W>x<H>_d<D>", any size and disparity range.
+    lane_bytes: the size a lane aims at; its batch capacity is that over one
+      pair's bytes, between 1 and max_batch.
+    graphs: replay library-captured graphs (else eager stereo_solve_batch).
     check: compare every result with the pair solved alone (bit for bit)."""
 
-    def __init__(self, pairs, shapes=SHAPES, vol_dtype=None, lanes=2, max_batch=None, budget_bytes=64 << 30,
-                 radius=4, sigma_s=20.0, sigma_r=0.1, dt_iters=3, graphs=True, check=True, device="cuda"):
+    def __init__(self, pairs, vol_dtype=None, budget_bytes=64 * 10 ** 9, lane_bytes=1 << 30, max_batch=8,
+                 max_lanes_per_shape=4, radius=4, sigma_s=20.0, sigma_r=0.1, dt_iters=3, graphs=True, check=True,
+                 autotune_cache=None, device="cuda"):
         import torch
 
         from . import _lib as lib
         self.torch, self.lib = torch, lib
-        vol_dtype = lib.ZDT_F16 if vol_dtype is None else vol_dtype
-        self.shapes = {s.name: s for s in shapes if s.name in pairs}
-        max_batch = max_batch or {"640x192_d64": 8, "1280x384_d128": 8, "1920x1080_d256": 2}
-        self.max_batch = {s: max_batch.get(s, 4) for s in self.shapes}
-        self.nlanes = {s: (lanes[s] if isinstance(lanes, dict) else lanes) for s in self.shapes}
-        self.params = {s: lib.params(sh.W, sh.H, sh.D, radius, sigma_s, sigma_r, dt_iters, vol_dtype)
-                       for s, sh in self.shapes.items()}
-        vol_bytes = sum(self.nlanes[s] * self.max_batch[s] * lib.volume_size(self.params[s]) for s in self.shapes)
-        if vol_bytes > budget_bytes:
-            raise ValueError("lanes need %.2f GB of cost volumes, over the %.2f GB budget"
-                             % (vol_bytes / 1e9, budget_bytes / 1e9))
-        self.volume_bytes = vol_bytes
-        dev = torch.device(device)
+        self.vol_dtype = lib.ZDT_F16 if vol_dtype is None else vol_dtype
+        self.budget, self.lane_target, self.max_batch = budget_bytes, lane_bytes, max_batch
+        self.max_lanes = max_lanes_per_shape
+        self.pp = (radius, sigma_s, sigma_r, dt_iters)
+        self.use_graphs, self.check, self.autotune_cache = graphs, check, autotune_cache
+        self.dev = torch.device(device)
+        self.params, self.lanes, self.alone = {}, {}, {}
+        self.graph_captures = 0
         self.pinned = {s: [(torch.from_numpy(p.left).pin_memory(), torch.from_numpy(p.right).pin_memory())
-                           for p in pairs[s]] for s in self.shapes}
-        vt = {lib.ZDT_F32: torch.float32, lib.ZDT_F16: torch.float16, lib.ZDT_BF16: torch.bfloat16}[vol_dtype]
-        self.lanes = {}
-        for s, sh in self.shapes.items():
-            p, B = self.params[s], self.max_batch[s]
-            wsz = lib.workspace_size(p)
-            for k in range(self.nlanes[s]):
-                u8 = dict(dtype=torch.uint8, device=dev)
-                left, right = torch.empty((B, sh.H, sh.W), **u8), torch.empty((B, sh.H, sh.W), **u8)
-                disp = torch.empty((B, sh.H, sh.W), dtype=torch.int32, device=dev)
-                vols = [torch.empty((sh.H, sh.W, sh.D), dtype=vt, device=dev) for _ in range(B)]
-                wss = [torch.empty(wsz, **u8) if wsz else None for _ in range(B)]
-                jobs = [(p, left[i], right[i], disp[i], vols[i], wss[i]) for i in range(B)]
-                host_out = torch.empty((B, sh.H, sh.W), dtype=torch.int32).pin_memory()
-                self.lanes[(s, k)] = _Lane(sh, torch.cuda.Stream(device=dev), left, right, disp, host_out, vols, wss,
-                                           jobs, torch.cuda.Event())
-        self.use_graphs = graphs
-        self.check = check
-        self.alone = {}
+                           for p in ps] for s, ps in pairs.items()}
         if check:
-            for s in self.shapes:
+            for s in self.pinned:
                 self.alone[s] = [self._solve_alone(s, i) for i in range(len(self.pinned[s]))]
-        if graphs:
-            self._capture()
+
+    # -- shapes
+    def _params(self, s):
+        if s not in self.params:
+            sh = shape_of(s)
+            p = self.lib.params(sh.W, sh.H, sh.D, *self.pp, vol_dtype=self.vol_dtype)
+            if self.autotune_cache:
+                self.lib.autotune(p, self.autotune_cache)
+            self.params[s] = p
+        return self.params[s]
+
+    def pair_bytes(self, s):
+        sh, p = shape_of(s), self._params(s)
+        return self.lib.volume_size(p) + self.lib.workspace_size(p) + sh.W * sh.H * (2 + 4)
+
+    def lane_plan(self, s):
+        per = self.pair_bytes(s)
+        cap = max(1, min(self.max_batch, self.lane_target // per))
+        return cap, cap * per
+
+    def scheduler(self):
+        return Scheduler(self, self.budget, self.max_lanes)
+
+    # -- lanes
+    def create_lane(self, lane_id, s, cap):
+        torch, lib = self.torch, self.lib
+        sh, p = shape_of(s), self._params(s)
+        wsz = lib.workspace_size(p)
+        u8 = dict(dtype=torch.uint8, device=self.dev)
+        left, right = torch.empty((cap, sh.H, sh.W), **u8), torch.empty((cap, sh.H, sh.W), **u8)
+        disp = torch.empty((cap, sh.H, sh.W), dtype=torch.int32, device=self.dev)
+        vols = [torch.empty(lib.volume_size(p), **u8) for _ in range(cap)]
+        wss = [torch.empty(wsz, **u8) if wsz else None for _ in range(cap)]
+        jobs = [(p, left[i], right[i], disp[i], vols[i], wss[i]) for i in range(cap)]
+        host_out = torch.empty((cap, sh.H, sh.W), dtype=torch.int32).pin_memory()
+        self.lanes[lane_id] = _Lane(sh, torch.cuda.Stream(device=self.dev), left, right, disp, host_out, vols, wss,
+                                    jobs, torch.cuda.Event())
+
+    def destroy_lane(self, lane_id):
+        lane = self.lanes.pop(lane_id)
+        lane.stream.synchronize()
+        for g in lane.graphs.values():
+            g.close()
 
     def _solve_alone(self, s, i):
-        torch, lib, sh = self.torch, self.lib, self.shapes[s]
-        p = self.params[s]
-        left, right = (t.cuda() for t in self.pinned[s][i])
-        disp = torch.empty((sh.H, sh.W), dtype=torch.int32, device="cuda")
-        vol = torch.empty(lib.volume_size(p), dtype=torch.uint8, device="cuda")
+        torch, lib = self.torch, self.lib
+        sh, p = shape_of(s), self._params(s)
+        left, right = (t.to(self.dev) for t in self.pinned[s][i])
+        disp = torch.empty((sh.H, sh.W), dtype=torch.int32, device=self.dev)
+        vol = torch.empty(lib.volume_size(p), dtype=torch.uint8, device=self.dev)
         wsz = lib.workspace_size(p)
-        ws = torch.empty(wsz, dtype=torch.uint8, device="cuda") if wsz else None
+        ws = torch.empty(wsz, dtype=torch.uint8, device=self.dev) if wsz else None
         lib.stereo_solve(p, left, right, disp, vol, ws)
         out = disp.cpu().numpy()
         del vol, ws
         return out
-
-    def _capture(self):
-        torch, lib = self.torch, self.lib
-        for lane in self.lanes.values():
-            for n in range(1, self.max_batch[lane.shape.name] + 1):
-                with torch.cuda.stream(lane.stream):     # warm-up outside the capture
-                    lib.stereo_solve_batch(lane.jobs[:n], stream=lane.stream)
-                lane.stream.synchronize()
-                g = torch.cuda.CUDAGraph()
-                with torch.cuda.graph(g, stream=lane.stream):
-                    lib.stereo_solve_batch(lane.jobs[:n], stream=torch.cuda.current_stream())
-                lane.graphs[n] = g
-        torch.cuda.synchronize()
 
     def launch(self, lane_id, batch):
         torch, lane = self.torch, self.lanes[lane_id]
@@ -270,13 +380,15 @@ class GpuExecutor:
                 src_l, src_r = self.pinned[r.shape][r.pair]
                 lane.left[k].copy_(src_l, non_blocking=True)
                 lane.right[k].copy_(src_r, non_blocking=True)
-            if self.use_graphs:
-                lane.graphs[n].replay()
-            else:
+            if not self.use_graphs:
                 self.lib.stereo_solve_batch(lane.jobs[:n], stream=lane.stream)
+            elif n in lane.graphs:
+                lane.graphs[n].launch(lane.stream)
+            else:   # capturing runs the batch once, eagerly, before recording it
+                lane.graphs[n] = self.lib.Graph(lane.jobs[:n], lane.stream)
+                self.graph_captures += 1
             lane.host_out[:n].copy_(lane.disp[:n], non_blocking=True)
             lane.event.record(lane.stream)
-        lane.batch = batch
 
     def poll(self, lane_id):
         return self.lanes[lane_id].event.query()
@@ -288,9 +400,6 @@ class GpuExecutor:
         for k, r in enumerate(batch):
             r.ok = bool(np.array_equal(lane.host_out[k].numpy(), self.alone[r.shape][r.pair]))
 
-    def scheduler(self):
-        return Scheduler(self.nlanes, self.max_batch)
-
 
 def per_pair_capacity(reqs, pairs, vol_dtype, radius=4, sigma_s=20.0, sigma_r=0.1, dt_iters=3):
     """Pairs per second of the plain form: the same requests solved one at a
@@ -300,7 +409,7 @@ def per_pair_capacity(reqs, pairs, vol_dtype, radius=4, sigma_s=20.0, sigma_r=0.
     from . import _lib as lib
     bufs = {}
     for name in {r.shape for r in reqs}:
-        sh = next(s for s in SHAPES if s.name == name)
+        sh = shape_of(name)
         p = lib.params(sh.W, sh.H, sh.D, radius, sigma_s, sigma_r, dt_iters, vol_dtype)
         wsz = lib.workspace_size(p)
         bufs[name] = (p, torch.empty((sh.H, sh.W), dtype=torch.uint8, device="cuda"),
@@ -323,41 +432,58 @@ def per_pair_capacity(reqs, pairs, vol_dtype, radius=4, sigma_s=20.0, sigma_r=0.
     return len(reqs) / (time.perf_counter() - t0)
 
 
-def make_pairs(per_shape, shapes=SHAPES, seed=1000):
-    """Input pools: `per_shape[name]` synthetic scenes of each shape."""
+def _one_pair(args):
     from . import scenes
-    return {s.name: [scenes.planes_pair(s.W, s.H, s.D, seed=seed + 17 * i + s.W) for i in range(per_shape[s.name])]
-            for s in shapes if per_shape.get(s.name, 0) > 0}
+    w, h, d, seed = args
+    return scenes.planes_pair(w, h, d, seed=seed)
 
 
-def run(rate=300.0, duration=10.0, vol_dtype=None, pairs_per_shape=None, lanes=2, graphs=True, check=True, seed=0,
-        autotune=True):
-    """Serve a Poisson stream of the mixed shapes and summarise it."""
-    from . import _lib as lib
-    pairs_per_shape = pairs_per_shape or {"640x192_d64": 4, "1280x384_d128": 2, "1920x1080_d256": 1}
-    pairs = make_pairs(pairs_per_shape)
-    if autotune:
-        vd = lib.ZDT_F16 if vol_dtype is None else vol_dtype
-        for s in SHAPES:
-            if s.name in pairs:
-                lib.autotune(lib.params(s.W, s.H, s.D, vol_dtype=vd))
-    ex = GpuExecutor(pairs, vol_dtype=vol_dtype, lanes=lanes, graphs=graphs, check=check)
-    reqs = poisson_arrivals(rate, duration, MIX, {k: len(v) for k, v in pairs.items()}, seed=seed)
-    serve(reqs, ex.scheduler(), ex)
-    out = summarize(reqs)
-    out.update({"offered_rate": rate, "duration_s": duration, "volume_gb": round(ex.volume_bytes / 1e9, 2),
+def make_pairs(per_shape, shapes=SHAPES, seed=1000, workers=1):
+    """Input pools: `per_shape[name]` synthetic scenes of each shape (seeds
+    seed + 17 i + W), generated on `workers` processes."""
+    jobs = [(s.name, (s.W, s.H, s.D, seed + 17 * i + s.W)) for s in shapes for i in range(per_shape.get(s.name, 0))]
+    if workers > 1 and len(jobs) > 1:
+        import multiprocessing as mp
+        from concurrent.futures import ProcessPoolExecutor
+        with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+            made = list(ex.map(_one_pair, [a for _, a in jobs]))
+    else:
+        made = [_one_pair(a) for _, a in jobs]
+    out = {}
+    for (name, _), pr in zip(jobs, made):
+        out.setdefault(name, []).append(pr)
+    return out
+
+
+def run(rate=300.0, duration=60.0, vol_dtype=None, pairs_per_shape=64, graphs=True, check=True, seed=7, workers=16,
+        progress=None):
+    """Serve a Poisson stream of the mixed shapes (pools of `pairs_per_shape`
+    seeded pairs each, generated before the clock starts) and summarise it."""
+    pools = make_pairs({s.name: pairs_per_shape for s in SHAPES}, workers=workers)
+    ex = GpuExecutor(pools, vol_dtype=vol_dtype, graphs=graphs, check=check)
+    sched = ex.scheduler()
+    reqs = poisson_arrivals(rate, duration, MIX, {k: len(v) for k, v in pools.items()}, seed=seed)
+    serve(reqs, sched, ex, progress=progress)
+    out = summarize(reqs, duration=duration)
+    out.update({"offered_per_s": rate, "seconds": duration, "pairs_per_shape": pairs_per_shape,
+                "budget_gb": round(ex.budget / 1e9, 2), "peak_lane_bytes_gb": round(sched.peak / 1e9, 3),
+                "lanes_opened": {s: n for s, n in sched._next.items()}, "graph_captures": ex.graph_captures,
+                "waited_for_memory": len(sched.waited_for_memory), "lanes_released": sched.released,
                 "graphs": graphs})
+    sched.close()
     return out
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--rate", type=float, default=300.0)
-    ap.add_argument("--duration", type=float, default=10.0)
+    ap.add_argument("--duration", type=float, default=60.0)
+    ap.add_argument("--pairs", type=int, default=64)
     ap.add_argument("--no-graphs", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     args = ap.parse_args()
-    print(json.dumps(run(args.rate, args.duration, graphs=not args.no_graphs, check=not args.no_check)))
+    print(json.dumps(run(args.rate, args.duration, pairs_per_shape=args.pairs, graphs=not args.no_graphs,
+                         check=not args.no_check)))
 
 
 if __name__ == "__main__":

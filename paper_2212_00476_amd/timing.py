@@ -22,6 +22,11 @@ def main(argv=None):
     ap.add_argument("workload", help="planes_1280x384_d128, planes_1920x1080_d256, planes_640x192_d64, ...")
     ap.add_argument("--dtype", action="append", choices=DTYPES, help="volume type (repeatable; default f32)")
     ap.add_argument("--radius", type=int, default=4)
+    ap.add_argument("--plan", action="append", default=[],
+                    help="dtype:h_lanes,h_seg,v_lanes,v_seg -- pin a tile plan for that volume type (repeatable)")
+    ap.add_argument("--sigma-s", type=float, default=20.0)
+    ap.add_argument("--sigma-r", type=float, default=0.1)
+    ap.add_argument("--iters", type=int, default=3)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -30,7 +35,7 @@ def main(argv=None):
 
     import torch
 
-    from . import ZDT_BF16, ZDT_F16, ZDT_F32, ZDT_I8, ZDT_I16, Solver, params, profile_collect, profile_enable
+    from . import ZDT_BF16, ZDT_F16, ZDT_F32, ZDT_I8, ZDT_I16, Solver, params, profile_collect, profile_enable, set_plan
     from . import scenes
 
     codes = {"f32": ZDT_F32, "f16": ZDT_F16, "bf16": ZDT_BF16, "i16": ZDT_I16, "i8": ZDT_I8}
@@ -45,8 +50,12 @@ def main(argv=None):
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    plans = {k: tuple(int(v) for v in p.split(",")) for k, p in (x.split(":") for x in args.plan)}
     for name in args.dtype or ["f32"]:
-        solver = Solver(params(W, H, D, args.radius, vol_dtype=codes[name]))
+        p = params(W, H, D, args.radius, args.sigma_s, args.sigma_r, args.iters, vol_dtype=codes[name])
+        if name in plans:
+            set_plan(p, plans[name])
+        solver = Solver(p)
         for _ in range(args.warmup):
             solver(left, right)
         torch.cuda.synchronize()
@@ -58,7 +67,8 @@ def main(argv=None):
         ms = (time.perf_counter() - t) / args.steps * 1e3
         profile_enable(False)
         kernels = {k: round(1e3 * v / n, 1) for k, (v, n) in profile_collect().items()}
-        print(f"{args.workload} {name}: {ms:.3f} ms per pair; kernel avg us {kernels}", flush=True)
+        plan = f" plan {plans[name]}" if name in plans else ""
+        print(f"{args.workload} {name}{plan}: {ms:.3f} ms per pair; kernel avg us {kernels}", flush=True)
         del solver
         torch.cuda.empty_cache()
 

@@ -11,7 +11,9 @@ import math
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libzdt.so")
+# ZDT_LIBRARY names another build of the same library (e.g. to compare two
+# builds side by side); by default the in-tree libzdt.so.
+LIB_PATH = os.environ.get("ZDT_LIBRARY") or os.path.join(HERE, "libzdt.so")
 
 ZDT_OK, ZDT_EINVAL, ZDT_ENOMEM, ZDT_EHIP, ZDT_EUNSUPPORTED = 0, -1, -2, -3, -4
 ZDT_F32, ZDT_F16, ZDT_BF16, ZDT_I16, ZDT_I8 = 0, 1, 2, 3, 4

@@ -35,7 +35,7 @@ SIGMA_S, SIGMA_R, ITERS = 20.0, 0.1, 3
 WORKLOAD = "planes_1280x384_d128"
 PEAK_HBM_GBS = 8000.0
 METRIC = "Gcost-evals/s & fps at 1280x384 D=128 (FP32 vs FP16 vol); p99 latency served"
-KERNEL_SOURCES = ("paper_2212_00476_amd/csrc/zdt_device.hpp",)
+KERNEL_SOURCES = ("paper_2212_00476_amd/csrc/zdt_device.hpp", "paper_2212_00476_amd/csrc/zdt_sgm.hip")
 
 
 def kernel_source_hash():

@@ -655,18 +655,45 @@ __device__ void line_pair_gain(const float* in, float* out, const float* w, int 
   }
 }
 
-// H workgroups that hold the two halves of the same 128-byte lines (chunks 2p
-// and 2p+1 of a row) get linear ids L and L+8: workgroups are dispatched to the
-// 8 XCDs round-robin, so such a pair runs on one XCD and shares its L2.
-struct HTile {
-  int y, chunk;
+// Workgroups are dispatched to the 8 XCDs round-robin by linear id, and each
+// XCD has its own L2.  The tiles of a pass (line, disparity chunk), line-major,
+// are dealt so that every XCD takes one contiguous range of them: the chunks of
+// one line (which share the line's guide pixels, gains and, in 16-bit volumes
+// with 32-lane segments, the two halves of each 128-byte volume line) and
+// neighbouring lines (which share the 128-byte lines of the column-strided
+// guide and gain maps in the V pass) then meet in one L2.  The grid is
+// kXcds * ceil(ntiles / kXcds) workgroups; `valid` is false for the padding.
+constexpr int kXcds = 8;
+struct Tile {
+  int line, chunk;
+  bool valid;
 };
-__device__ __forceinline__ HTile h_tile(int L, int H, int nchunks) {
+__host__ __device__ inline int xcd_grid(int ntiles) { return kXcds * ((ntiles + kXcds - 1) / kXcds); }
+__device__ __forceinline__ Tile xcd_tile(int L, int ntiles, int nchunks) {
+  const int per = (ntiles + kXcds - 1) / kXcds;
+  const int t = (L % kXcds) * per + L / kXcds;
+  return {t / nchunks, t % nchunks, t < ntiles};
+}
+// The 16-bit H passes instead only put the two chunks that hold the halves of
+// the same 128-byte lines (2p and 2p+1) on one XCD, at linear ids L and L + 8,
+// and keep the lines in order across XCDs (measured a little faster there).
+__host__ __device__ inline int pair_grid(int nlines, int nchunks) { return (nlines * ((nchunks + 1) / 2) + 7) / 8 * 16; }
+__device__ __forceinline__ Tile pair_tile(int L, int nlines, int nchunks) {
   const int npairs = (nchunks + 1) / 2;
   const int r = L & 15;
   const int i = (L >> 4) * 8 + (r & 7);
-  return {i / npairs, 2 * (i % npairs) + (r >> 3)};
+  const Tile t{i / npairs, 2 * (i % npairs) + (r >> 3), true};
+  return {t.line, t.chunk, t.line < nlines && t.chunk < nchunks};
 }
+// Which tile order a pass uses (measured per pass and element size at
+// 1280x384, D = 128 and 1920x1080, D = 256): the H passes of 16-bit volumes
+// pair_tile, the other H passes xcd_tile; the V passes of 16-bit volumes
+// xcd_tile (their column-strided gain maps), the other V passes the plain
+// order of a (chunk, column) grid.
+template <int BYTES>
+constexpr int h_order() { return BYTES == 2 ? 1 : 2; }  // 1: pair_tile, 2: xcd_tile
+template <int BYTES>
+constexpr int v_order() { return BYTES == 2 ? 2 : 0; }  // 2: xcd_tile, 0: (chunk, column) grid
 
 // Waves per SIMD the register allocator is asked to allow.  H pairs with two
 // segments of up to 40 values per wave are held to 64 VGPRs (spilling a few
@@ -700,10 +727,11 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
   static_assert(LPS == 64 || LPS == 32, "lanes per segment");
   constexpr uint32_t kBytes = sizeof(T);
   int y, chunk;
-  if constexpr (kDT && kBytes == 2) {
-    const HTile t = h_tile(blockIdx.x, a.H, a.nchunks);
-    if (t.y >= a.H || t.chunk >= a.nchunks) return;  // padding of the paired grid
-    y = t.y;
+  if constexpr (kDT) {
+    const Tile t = h_order<kBytes>() == 1 ? pair_tile(blockIdx.x, a.H, a.nchunks)
+                                          : xcd_tile(blockIdx.x, a.H * a.nchunks, a.nchunks);
+    if (!t.valid) return;  // padding of the grid
+    y = t.line;
     chunk = t.chunk;
   } else {
     y = blockIdx.y;
@@ -1139,10 +1167,10 @@ __global__ __launch_bounds__(1024) void vpass_kernel(VArgs args, VJobs jobs) {
   constexpr int SPW = kWave / LPS;
   constexpr uint32_t kBytes = sizeof(T);
   int chunk, x;
-  if constexpr (LPS == 32 && kBytes == 2) {
-    const HTile t = h_tile(blockIdx.x, a.W, a.nchunks);
-    if (t.y >= a.W || t.chunk >= a.nchunks) return;  // padding of the paired grid
-    x = t.y;
+  if constexpr (v_order<kBytes>() == 2) {
+    const Tile t = xcd_tile(blockIdx.x, a.W * a.nchunks, a.nchunks);
+    if (!t.valid) return;  // padding of the grid
+    x = t.line;
     chunk = t.chunk;
   } else {
     chunk = blockIdx.x;

@@ -20,11 +20,8 @@ int run_h(const HArgs& a, const HJobs& jobs, int n, hipStream_t s) {
   // the Int8 reference launch covers disparity chunk 0 only
   b.nchunks = a.ref_role == kRefL2ROut ? 1 : (a.D + LPS - 1) / LPS;
   dim3 grid(b.nchunks, a.H, n);
-  if constexpr ((MODE == kCostHPair || MODE == kHPair) && sizeof(T) == 2) {
-    // 1-D grid (per job) with the chunk pairs of a row on one XCD (see h_tile)
-    const int items = a.H * ((b.nchunks + 1) / 2);
-    grid = dim3((unsigned)((items + 7) / 8 * 16), 1, n);
-  }
+  if constexpr (kDT)  // tile order of the H pass (h_order)
+    grid = dim3((unsigned)(h_order<sizeof(T)>() == 1 ? pair_grid(a.H, b.nchunks) : xcd_grid(a.H * b.nchunks)), 1, n);
   return launch(names[MODE], hpass_kernel<R, SEG, LPS, T, MODE>, grid, dim3(kWave * nw), (size_t)lay.words * 4, s, b,
                 jobs);
 }
@@ -67,12 +64,8 @@ template <int SEG, bool FULL, typename T, int LPS, bool WTA>
 int run_v(const VArgs& a, const VJobs& jobs, int n, hipStream_t s) {
   VArgs b = a;
   b.nchunks = (a.D + LPS - 1) / LPS;
-  dim3 grid(b.nchunks, a.W, n);
-  if constexpr (LPS == 32 && sizeof(T) == 2) {
-    // 1-D grid (per job) with the chunk pairs of a column on one XCD (see h_tile)
-    const int items = a.W * ((b.nchunks + 1) / 2);
-    grid = dim3((unsigned)((items + 7) / 8 * 16), 1, n);
-  }
+  dim3 grid(b.nchunks, a.W, n);  // tile order of the V pass (v_order)
+  if constexpr (v_order<sizeof(T)>() == 2) grid = dim3((unsigned)xcd_grid(a.W * b.nchunks), 1, n);
   const int nw = a.nseg / (kWave / LPS);
   return launch(WTA ? "dt_vpair_wta" : "dt_vpair", vpass_kernel<SEG, FULL, T, LPS, WTA>, grid, dim3(kWave * nw),
                 (size_t)v_lds_words(a.H, SEG, std::is_same<T, f16x>::value, is_int_vol<T>()) * 4, s, b, jobs);

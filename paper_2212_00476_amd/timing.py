@@ -5,7 +5,9 @@
 Prints one line per volume type: milliseconds per pair (wall clock over
 `steps` solves after `warmup` untimed ones, default plan, 9x9 window, three
 sweeps) and each kernel's average time from HIP events that the library
-records on its launch stream.  Inputs stay resident on the device; nothing
+records on its launch stream.  sgm_f32 / sgm_f16 time the paper's system S1
+instead (ZNCC costs of that type, four-path SGM with P1 = 18, P2 = 185 on
+costs times 21, WTA).  Inputs stay resident on the device; nothing
 is checked (the tests do that).  Also serves as the program to run under
 rocprofv3 for a per-kernel summary of a workload.
 """
@@ -14,7 +16,7 @@ from __future__ import annotations
 import argparse
 import time
 
-DTYPES = ("f32", "f16", "bf16", "i16", "i8")
+DTYPES = ("f32", "f16", "bf16", "i16", "i8", "sgm_f32", "sgm_f16")
 
 
 def main(argv=None):
@@ -35,7 +37,8 @@ def main(argv=None):
 
     import torch
 
-    from . import ZDT_BF16, ZDT_F16, ZDT_F32, ZDT_I8, ZDT_I16, Solver, params, profile_collect, profile_enable, set_plan
+    from . import (ZDT_BF16, ZDT_F16, ZDT_F32, ZDT_I8, ZDT_I16, Solver, params, profile_collect, profile_enable,
+                   set_plan, stereo_solve_sgm, torch_dtype)
     from . import scenes
 
     codes = {"f32": ZDT_F32, "f16": ZDT_F16, "bf16": ZDT_BF16, "i16": ZDT_I16, "i8": ZDT_I8}
@@ -52,10 +55,20 @@ def main(argv=None):
         del src, dst
     plans = {k: tuple(int(v) for v in p.split(",")) for k, p in (x.split(":") for x in args.plan)}
     for name in args.dtype or ["f32"]:
-        p = params(W, H, D, args.radius, args.sigma_s, args.sigma_r, args.iters, vol_dtype=codes[name])
-        if name in plans:
-            set_plan(p, plans[name])
-        solver = Solver(p)
+        if name.startswith("sgm_"):
+            ct = codes[name[4:]]
+            p = params(W, H, D, args.radius, vol_dtype=ct)
+            cost = torch.empty((H, W, D), dtype=torch_dtype(ct), device="cuda")
+            sums = torch.empty((H, W, D), dtype=torch.float32, device="cuda")
+            disp = torch.empty((H, W), dtype=torch.int32, device="cuda")
+
+            def solver(left, right, p=p, cost=cost, sums=sums, disp=disp):
+                stereo_solve_sgm(p, left, right, disp, cost, sums, 18.0, 185.0, 21.0)
+        else:
+            p = params(W, H, D, args.radius, args.sigma_s, args.sigma_r, args.iters, vol_dtype=codes[name])
+            if name in plans:
+                set_plan(p, plans[name])
+            solver = Solver(p)
         for _ in range(args.warmup):
             solver(left, right)
         torch.cuda.synchronize()

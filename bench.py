@@ -285,6 +285,8 @@ def bench_batch(torch, zdt, reps=3):
     return {"workload": "16x 640x192 D64 + 24x 1280x384 D128 + 8x 1920x1080 D256, 9x9, FP16 volumes",
             "jobs": sum(BATCH.values()), "ms": round(ms_b, 3), "gcost_evals_per_s": round(evals / ms_b / 1e6, 2),
             "pairs_per_s": round(sum(BATCH.values()) / ms_b * 1e3, 1), "one_by_one_ms": round(ms_s, 3),
+            "batch_vs_one_by_one": round(ms_s / ms_b, 4),
+            "schedule": "pairs dealt largest-first over two library streams forked from the caller's stream",
             "plans": plans}
 
 

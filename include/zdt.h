@@ -153,10 +153,17 @@ typedef struct zdt_job {
   void* ws;
 } zdt_job;
 
-/* stereo_solve() for n pairs of mixed shapes on one stream, with the same
- * results as n separate calls.  Jobs with identical parameters share every
- * launch: each stage (cost + L/R pair, U/D pair, ...) runs as one grid over up
- * to 32 of them, so small pairs fill the GPU together.  (The paper solves one
+/* stereo_solve() for n pairs of mixed shapes, with the same results as n
+ * separate calls.  The pairs are dealt, largest first, over two streams that
+ * the library owns on the stream's GPU (default priority; created on the first
+ * batch, kept until the process ends), forked from `stream` and joined back to
+ * it with events: work enqueued on `stream` before the call is seen by every
+ * pair, and work enqueued after it sees every result.  Pairs on the two streams
+ * share the GPU, so one pair's launches fill the CUs while another's drain.
+ * Batches from several host threads on one GPU are enqueued one at a time.
+ * Under graph capture of `stream` the batch stays on `stream`, and jobs with
+ * identical parameters share every launch: each stage (cost + L/R pair, U/D
+ * pair, ...) runs as one grid over up to 32 of them.  (The paper solves one
  * pair at a time; its nearest analogue is the per-shape launch-configuration
  * sweep of Sec. V-B.)  All jobs are validated before anything is enqueued;
  * job i's error is reported with its index.  n = 0 does nothing. */

@@ -726,20 +726,62 @@ int stereo_solve_static_ws(const zdt_params* p, const uint8_t* left, const uint8
   return rc;
 }
 
-int stereo_solve_batch(const zdt_job* jobs, int32_t n, void* stream) {
-  if (n < 0 || (n > 0 && !jobs)) return fail(ZDT_EINVAL, "stereo_solve_batch: %d jobs at %p", n, (const void*)jobs);
-  for (int i = 0; i < n; ++i) {
-    const zdt_job& j = jobs[i];
-    int rc = check_job(&j.params, j.left, j.right, j.disp, j.vol, j.ws, "stereo_solve_batch");
-    if (rc) return fail(rc, "stereo_solve_batch: job %d: %s", i, zdt_last_error());
+}  // extern "C"
+
+namespace {
+// ---- concurrent batches: two library-owned streams per GPU
+// A batch is dealt over two streams forked from and joined back to the
+// caller's stream, so the pairs' kernels share the GPU: one pair's cost and
+// recursion launches fill the CUs while another's drain, and stages bound by
+// arithmetic run beside stages bound by memory.  The streams (default
+// priority, non-blocking) and events live until the process ends.
+constexpr int kSideStreams = 2;
+struct SideStreams {
+  hipStream_t s[kSideStreams] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kSideStreams] = {};
+  std::mutex mu;  // one batch at a time enqueues on a GPU's pair of streams
+};
+SideStreams g_side[kMaxDevices];
+std::mutex g_side_init_mu;
+
+int side_streams_for(hipStream_t stream, SideStreams** out, const char* who) {
+  int cur = -1, dev = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return fail(ZDT_EHIP, "%s: hipGetDevice failed", who);
+  dev = cur;
+  if (stream && hipStreamGetDevice(stream, &dev) != hipSuccess)
+    return fail(ZDT_EHIP, "%s: hipStreamGetDevice failed", who);
+  if (dev < 0 || dev >= kMaxDevices) return fail(ZDT_EUNSUPPORTED, "%s: device %d", who, dev);
+  std::lock_guard<std::mutex> lk(g_side_init_mu);
+  SideStreams& ss = g_side[dev];
+  if (!ss.fork) {
+    if (dev != cur && hipSetDevice(dev) != hipSuccess) return fail(ZDT_EHIP, "%s: hipSetDevice(%d) failed", who, dev);
+    bool ok = true;
+    for (int k = 0; k < kSideStreams && ok; ++k)
+      ok = (ss.s[k] || hipStreamCreateWithFlags(&ss.s[k], hipStreamNonBlocking) == hipSuccess) &&
+           (ss.join[k] || hipEventCreateWithFlags(&ss.join[k], hipEventDisableTiming) == hipSuccess);
+    // the fork event is made last: its presence marks the set complete
+    if (ok) ok = hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming) == hipSuccess;
+    if (dev != cur) (void)hipSetDevice(cur);
+    if (!ok) return fail(ZDT_EHIP, "%s: creating the batch streams on device %d failed", who, dev);
   }
-  hipStream_t s = (hipStream_t)stream;
+  *out = &ss;
+  return ZDT_OK;
+}
+
+int solve_one(const zdt_job& j, hipStream_t s) {
+  const JobPtrs p{j.left, j.right, j.disp, j.vol, j.ws};
+  return j.params.dt_iters == 0 ? solve_raw(&j.params, p, s) : solve_group(&j.params, &p, 1, s);
+}
+
+// Jobs with identical parameters share each stage's launch (up to kMaxJobs per
+// grid), in submission order, all on `s`.
+int solve_grouped(const zdt_job* jobs, int n, hipStream_t s) {
   std::vector<char> done(n, 0);
   std::vector<JobPtrs> group;
   for (int i = 0; i < n; ++i) {
     if (done[i]) continue;
     const zdt_params& p = jobs[i].params;
-    // jobs with identical parameters, in submission order, kMaxJobs per launch
     group.clear();
     for (int k = i; k < n; ++k) {
       if (done[k] || std::memcmp(&jobs[k].params, &p, sizeof p) != 0) continue;
@@ -758,6 +800,62 @@ int stereo_solve_batch(const zdt_job* jobs, int32_t n, void* stream) {
     }
   }
   return ZDT_OK;
+}
+
+// Largest job first, each to the side stream with less work queued so far
+// (work: cost values times the passes over them).
+int solve_concurrent(const zdt_job* jobs, int n, hipStream_t s, SideStreams& ss) {
+  std::vector<int> order(n);
+  std::vector<double> work(n);
+  for (int i = 0; i < n; ++i) {
+    const zdt_params& p = jobs[i].params;
+    order[i] = i;
+    work[i] = (double)p.width * p.height * p.max_disp * (1 + 2 * p.dt_iters);
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+  if (hipEventRecord(ss.fork, s) != hipSuccess) return fail(ZDT_EHIP, "stereo_solve_batch: hipEventRecord failed");
+  for (int k = 0; k < kSideStreams; ++k)
+    if (hipStreamWaitEvent(ss.s[k], ss.fork, 0) != hipSuccess)
+      return fail(ZDT_EHIP, "stereo_solve_batch: hipStreamWaitEvent failed");
+  double queued[kSideStreams] = {};
+  int rc = ZDT_OK;
+  for (int i : order) {
+    int k = 0;
+    for (int q = 1; q < kSideStreams; ++q)
+      if (queued[q] < queued[k]) k = q;
+    queued[k] += work[i];
+    if ((rc = solve_one(jobs[i], ss.s[k]))) break;
+  }
+  // join even after an error, so that later work on `s` stays ordered after
+  // whatever was enqueued
+  for (int k = 0; k < kSideStreams; ++k)
+    if (hipEventRecord(ss.join[k], ss.s[k]) != hipSuccess || hipStreamWaitEvent(s, ss.join[k], 0) != hipSuccess)
+      if (rc == ZDT_OK) rc = fail(ZDT_EHIP, "stereo_solve_batch: joining the batch streams failed");
+  return rc;
+}
+}  // namespace
+
+extern "C" {
+
+int stereo_solve_batch(const zdt_job* jobs, int32_t n, void* stream) {
+  if (n < 0 || (n > 0 && !jobs)) return fail(ZDT_EINVAL, "stereo_solve_batch: %d jobs at %p", n, (const void*)jobs);
+  for (int i = 0; i < n; ++i) {
+    const zdt_job& j = jobs[i];
+    int rc = check_job(&j.params, j.left, j.right, j.disp, j.vol, j.ws, "stereo_solve_batch");
+    if (rc) return fail(rc, "stereo_solve_batch: job %d: %s", i, zdt_last_error());
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if (n < 2) return n == 1 ? solve_one(jobs[0], s) : ZDT_OK;
+  // Under graph capture (and in the no-allocation path) the batch stays on
+  // the caller's stream: grouped launches, no library streams in the graph.
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) return fail(ZDT_EHIP, "stereo_solve_batch: hipStreamIsCapturing failed");
+  if (g_no_alloc || cs != hipStreamCaptureStatusNone) return solve_grouped(jobs, n, s);
+  SideStreams* ss = nullptr;
+  int rc = side_streams_for(s, &ss, "stereo_solve_batch");
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(ss->mu);
+  return solve_concurrent(jobs, n, s, *ss);
 }
 
 namespace {

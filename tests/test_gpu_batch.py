@@ -1,8 +1,9 @@
 """Multi-job launches, tile plans and the autotuner on the GPU.
 
   - stereo_solve_batch gives, job for job, the same bits as separate
-    stereo_solve calls (mixed shapes, types and sweep counts; more jobs of one
-    shape than one launch takes);
+    stereo_solve calls (mixed shapes, types and sweep counts), ordered on the
+    caller's stream, also with batches from two host threads at once, and, under
+    graph capture, with more jobs of one shape than one launch takes;
   - every tile plan a shape admits agrees with the FP64 oracle to the usual
     end-to-end bar (FP32: mismatches only at near-ties of the oracle's own
     aggregated costs; FP16: <= 0.1 % of disparities);
@@ -82,7 +83,7 @@ def test_batch_equals_separate_calls_mixed():
         assert torch.equal(got[i], alone), i
 
 
-def test_batch_more_jobs_than_one_launch():
+def test_batch_many_jobs_of_one_shape():
     n = 35
     note("batch of %d jobs of one shape" % n)
     jobs = [Job(64, 24, 16, 2, zdt.ZDT_F16, 3, seed=100 + i) for i in range(n)]
@@ -91,6 +92,77 @@ def test_batch_more_jobs_than_one_launch():
     got = [j.disp.clone() for j in jobs]
     for i, j in enumerate(jobs):
         assert torch.equal(got[i], j.solve_alone()), i
+
+
+def test_batch_is_ordered_on_the_callers_stream():
+    """The batch runs on the library's two streams, forked from and joined back
+    to the caller's stream: images written on that stream just before the call
+    are the ones solved, and work queued after it sees the finished
+    disparities, with no synchronization in between."""
+    jobs = [Job(*m, seed=40 + i) for i, m in enumerate(MIX[:6])]
+    other = [Job(*m, seed=60 + i) for i, m in enumerate(MIX[:6])]
+    want = [o.solve_alone() for o in other]        # the images the batch will be given
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for j, o in zip(jobs, other):
+            j.left.copy_(o.left)
+            j.right.copy_(o.right)
+        zdt.stereo_solve_batch([j.tuple() for j in jobs], stream=s)
+        got = [j.disp.clone() for j in jobs]
+    s.synchronize()
+    for i in range(len(jobs)):
+        assert torch.equal(got[i], want[i]), i
+
+
+def test_batches_from_two_threads():
+    """Two host threads submit batches on their own streams at once; each job
+    still equals its pair solved alone."""
+    import threading
+    sets = [[Job(*m, seed=80 + 10 * t + i) for i, m in enumerate(MIX[:5])] for t in range(2)]
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    errors = []
+
+    def work(t):
+        try:
+            for _ in range(3):
+                zdt.stereo_solve_batch([j.tuple() for j in sets[t]], stream=streams[t])
+        except Exception as e:   # reported below, from the main thread
+            errors.append(e)
+    th = [threading.Thread(target=work, args=(t,)) for t in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    torch.cuda.synchronize()
+    assert not errors, errors
+    for jobs in sets:
+        got = [j.disp.clone() for j in jobs]
+        for i, j in enumerate(jobs):
+            assert torch.equal(got[i], j.solve_alone()), i
+
+
+def test_captured_batch_groups_more_jobs_than_one_launch():
+    """Under graph capture the batch stays on the capturing stream, with jobs of
+    identical parameters sharing each stage's launch (35 jobs: two launches per
+    stage); replays equal the pairs solved alone."""
+    n = 35
+    jobs = [Job(64, 24, 16, 2, zdt.ZDT_F16, 3, seed=200 + i) for i in range(n)] + \
+        [Job(100, 17, 65, 3, zdt.ZDT_F32, 3, seed=300)]
+    s = torch.cuda.Stream()
+    g = zdt.Graph([j.tuple() for j in jobs], s)
+    try:
+        for _ in range(2):
+            for j in jobs:
+                j.disp.fill_(-1)
+            torch.cuda.synchronize()
+            g.launch(s)
+            s.synchronize()
+            got = [j.disp.clone() for j in jobs]
+            for i, j in enumerate(jobs):
+                assert torch.equal(got[i], j.solve_alone()), i
+    finally:
+        g.close()
 
 
 def _near_tie_ok(disp, cagg):

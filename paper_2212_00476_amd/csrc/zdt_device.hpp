@@ -1144,10 +1144,25 @@ __device__ __forceinline__ void bfly_stage(uint32_t (&r)[N], int n, int lane) {
 // disparities, optionally followed by the WTA.  A wave holds 64 / LPS segments
 // of the column, each LPS lanes wide (consecutive disparities).  FULL: every
 // segment holds exactly SEG rows (checked by the host; required for LPS = 32).
-// 16-bit volumes with LPS = 32 use the XCD-paired 1-D grid of the H pass, so
-// the two workgroups writing the halves of the same 128-byte lines share an L2.
+// 16-bit volumes take the XCD-contiguous tile order (xcd_tile), so the
+// workgroups of a column's chunks and of neighbouring columns share an L2.
+//
+// Waves per SIMD the register allocator is asked to allow.  Two 32-lane
+// segments of up to 36 rows per wave are held to 64 VGPRs, so two 15-wave
+// workgroups of a 1080-row column share a CU (without the bound the 16-bit
+// loads and their FP32 values are both kept live and one workgroup fills the
+// CU); so are the gain-scaled FP16 U/D pairs with 64-lane segments of up to 48
+// rows (four 8-wave workgroups per CU instead of three).  The integer volumes
+// keep the default: under the bound their codecs spill.
+template <int SEG, int LPS, bool WTA, typename T>
+constexpr int v_waves_per_eu() {
+  if constexpr (is_int_vol<T>()) return 4;
+  if constexpr (LPS == 32 && SEG <= 36) return 8;
+  return (LPS == 64 && SEG <= 48 && !WTA && std::is_same<T, f16x>::value) ? 8 : 4;
+}
+
 template <int SEG, bool FULL, typename T, int LPS, bool WTA>
-__global__ __launch_bounds__(1024) void vpass_kernel(VArgs args, VJobs jobs) {
+__global__ __launch_bounds__(1024, (v_waves_per_eu<SEG, LPS, WTA, T>())) void vpass_kernel(VArgs args, VJobs jobs) {
   extern __shared__ uint32_t smem[];
   VArgs a = args;
   {

@@ -216,10 +216,12 @@ Split v_split_plan(int H, const Plan& pl) {
 // number of full segments, else 64-lane segments; the shortest 64-lane V
 // segments that cover the column with 8 waves (measured faster than 16 shorter
 // ones: fewer carries to compose, more workgroups per CU), else with up to 16
-// waves -- except that FP32 volumes then take two 32-lane segments per wave
-// when the column splits into an even number of full ones (at 1080 rows: a
-// solve 1.6 % faster, two workgroups per CU instead of one; 16-bit volumes,
-// whose 32-lane accesses move half lines, measured 5 % slower that way).
+// waves -- except that the floating-point volumes then take two 32-lane
+// segments per wave when the column splits into an even number of full ones:
+// at 1080 rows two such workgroups share a CU where one 15-wave 64-lane
+// workgroup fills it (1920x1080, D = 256: FP32 1.6 %, FP16 3.3 %, BF16 2.7 %
+// faster per solve).  The integer volumes keep 64-lane segments (their 32-lane
+// V kernels would need more than 64 VGPRs for two workgroups per CU).
 Plan default_plan(const zdt_params* p) {
   Plan pl{};
   if (const int s32 = h_full_seg32(p->width)) {
@@ -233,7 +235,7 @@ Plan default_plan(const zdt_params* p) {
   pl.v_seg = split_line(p->height, kVSegs, kNumVSegs, kMaxWaves / 2).seg;
   if (!pl.v_seg) {
     pl.v_seg = split_line(p->height, kVSegs, kNumVSegs, kMaxWaves).seg;
-    if (p->vol_dtype == ZDT_F32)
+    if (!int_vol(p->vol_dtype))
       for (int seg : kVSegs32)
         if (v_plan_ok(p->height, 32, seg)) {
           pl.v_lanes = 32;

@@ -43,11 +43,13 @@ def test_known_candidates():
     assert zdt.plan_candidates(p)[0] == (32, 40, 64, 48)   # 8 waves of 48 rows
     v = {(32, 12), (32, 24), (64, 24), (64, 48), (64, 72)}   # 384 = 32 x 12 = 16 x 24
     assert set(zdt.plan_candidates(p)) == {h + vv for h in ((32, 40), (64, 80)) for vv in v}
-    # 1080 rows: no 8-wave split; 16-bit volumes default to 15 waves of 72 rows with 30 half-waves of 36
-    # as the other candidate, FP32 volumes the other way round
-    assert zdt.plan_candidates(zdt.params(1920, 1080, 256, vol_dtype=zdt.ZDT_F16)) == [(32, 60, 64, 72),
-                                                                                      (32, 60, 32, 36)]
-    assert zdt.plan_candidates(zdt.params(1920, 1080, 256)) == [(32, 60, 32, 36), (32, 60, 64, 72)]
+    # 1080 rows: no 8-wave split; the floating-point volumes default to 30 half-waves of 36 rows with 15
+    # waves of 72 as the other candidate, the integer volumes the other way round
+    for dt in (zdt.ZDT_F32, zdt.ZDT_F16, zdt.ZDT_BF16):
+        assert zdt.plan_candidates(zdt.params(1920, 1080, 256, vol_dtype=dt)) == [(32, 60, 32, 36), (32, 60, 64, 72)]
+    for dt in (zdt.ZDT_I16, zdt.ZDT_I8):
+        p = zdt.params(1920, 1080, 256, sigma_s=5.0, dt_iters=1, vol_dtype=dt)
+        assert zdt.plan_candidates(p) == [(32, 60, 64, 72), (32, 60, 32, 36)]
 
 
 def test_set_plan_round_trip_and_rejects_misfits():

@@ -64,8 +64,7 @@ template <int SEG, bool FULL, typename T, int LPS, bool WTA>
 int run_v(const VArgs& a, const VJobs& jobs, int n, hipStream_t s) {
   VArgs b = a;
   b.nchunks = (a.D + LPS - 1) / LPS;
-  dim3 grid(b.nchunks, a.W, n);  // tile order of the V pass (v_order)
-  if constexpr (v_order<sizeof(T)>() == 2) grid = dim3((unsigned)xcd_grid(a.W * b.nchunks), 1, n);
+  const dim3 grid((unsigned)xcd_grid(a.W * b.nchunks), 1, n);  // (column, chunk) tiles in xcd_tile order
   const int nw = a.nseg / (kWave / LPS);
   return launch(WTA ? "dt_vpair_wta" : "dt_vpair", vpass_kernel<SEG, FULL, T, LPS, WTA>, grid, dim3(kWave * nw),
                 (size_t)v_lds_words(a.H, SEG, std::is_same<T, f16x>::value, is_int_vol<T>()) * 4, s, b, jobs);

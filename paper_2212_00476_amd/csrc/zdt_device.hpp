@@ -729,8 +729,8 @@ __global__ __launch_bounds__(1024, (h_waves_per_eu<R, SEG, LPS, MODE>())) void h
     const Tile t = h_order<kBytes>() == 1 ? pair_tile(blockIdx.x, a.H, a.nchunks)
                                           : xcd_tile(blockIdx.x, a.H * a.nchunks, a.nchunks);
     if (!t.valid) return;  // padding of the grid
-    y = t.line;
-    chunk = t.chunk;
+    y = __builtin_amdgcn_readfirstlane(t.line);  // the workgroup's tile, in SGPRs
+    chunk = __builtin_amdgcn_readfirstlane(t.chunk);
   } else {
     y = blockIdx.y;
     chunk = blockIdx.x;
@@ -1181,7 +1181,8 @@ __global__ __launch_bounds__(1024, (v_waves_per_eu<SEG, LPS, WTA, T>())) void vp
   constexpr uint32_t kBytes = sizeof(T);
   const Tile t = xcd_tile(blockIdx.x, a.W * a.nchunks, a.nchunks);
   if (!t.valid) return;  // padding of the grid
-  const int x = t.line, chunk = t.chunk;
+  // the tile is the workgroup's: kept in SGPRs (the division leaves it in VGPRs)
+  const int x = __builtin_amdgcn_readfirstlane(t.line), chunk = __builtin_amdgcn_readfirstlane(t.chunk);
   const int d0 = chunk * LPS;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -1216,8 +1217,9 @@ __global__ __launch_bounds__(1024, (v_waves_per_eu<SEG, LPS, WTA, T>())) void vp
   const int len = FULL ? SEG : min(a.segl, H - y0);  // >= 1; wave-uniform
   const uint32_t rowbytes = (uint32_t)W * D * kBytes;
   // buffer over the volume from column x on; every offset below stays inside it
-  const rsrc_t vrs = make_rsrc((const char*)a.vol + (size_t)x * D * kBytes,
-                               (uint32_t)((size_t)H * W * D * kBytes - (size_t)x * D * kBytes));
+  // 32-bit offsets: the host admits volumes below 4 GiB
+  const uint32_t col0 = (uint32_t)x * (uint32_t)D * kBytes;
+  const rsrc_t vrs = make_rsrc((const char*)a.vol + col0, (uint32_t)H * W * D * kBytes - col0);
   constexpr bool scaled = kHalf;
   if constexpr (scaled && !WTA) {
     // the column's gain after this pair, by the last wave (read after two barriers)
@@ -1240,9 +1242,18 @@ __global__ __launch_bounds__(1024, (v_waves_per_eu<SEG, LPS, WTA, T>())) void vp
     return (uint32_t)k * rowbytes;
   };
 
+  // Scaled FP16 values are loaded as raw bits and converted in loop A, so
+  // each 16-bit value's register is free once its FP32 value exists (loaded
+  // and converted at once, both sets were live together and the 64-VGPR
+  // bound of 36-row segments spilled).
   float c[SEG];
 #pragma unroll
-  for (int k = 0; k < SEG; ++k) c[k] = Elem<T>::bload(vrs, voff, step_off(k));
+  for (int k = 0; k < SEG; ++k) {
+    if constexpr (scaled)
+      c[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b16(vrs, (int)voff, (int)step_off(k), 0));
+    else
+      c[k] = Elem<T>::bload(vrs, voff, step_off(k));
+  }
   __builtin_amdgcn_sched_barrier(0);
   // ---- loop A: carry-free U pass (decoding scaled FP16 values on the way;
   // Int16's first sweep subtracts the stored R2L output's d = 0 slice first)
@@ -1253,7 +1264,8 @@ __global__ __launch_bounds__(1024, (v_waves_per_eu<SEG, LPS, WTA, T>())) void vp
   for (int k = 0; k < SEG; ++k) {
     const bool in = k < len;
     const float w = wp[k];
-    if constexpr (scaled) c[k] *= si[k];
+    if constexpr (scaled)
+      c[k] = (float)__builtin_bit_cast(_Float16, (unsigned short)__float_as_uint(c[k])) * si[k];
     if constexpr (kInt)
       if (sub_ref) c[k] -= rf[k];
     ell = in ? fmaf(w, ell, c[k]) : ell;
@@ -1400,12 +1412,12 @@ __global__ __launch_bounds__(1024, (v_waves_per_eu<SEG, LPS, WTA, T>())) void vp
     for (int r = 0; r < NR; ++r) {
       const int k = r * LPS + dloc;
       if (k < len) {
-        const size_t p = (size_t)(y0 + k) * W + x;
+        const uint32_t p = (uint32_t)(y0 + k) * W + x;  // < W H
         if (a.disp) {
           a.disp[p] = rd[r];
         } else {
           // column-major partials: the wave's rows are consecutive words
-          const size_t q = (size_t)chunk * W * H + (size_t)x * H + (y0 + k);
+          const uint32_t q = ((uint32_t)chunk * W + x) * H + (y0 + k);  // < ceil(D / 32) W H
           a.part_val[q] = kInt ? key_value(rv[r]) : __uint_as_float(rv[r]);
           a.part_idx[q] = rd[r];
         }

@@ -213,7 +213,8 @@ Split v_split_plan(int H, const Plan& pl) {
 }
 
 // Default plan: two 32-lane segments per wave when the row splits into an even
-// number of full segments, else 64-lane segments; the shortest 64-lane V
+// number of full segments (of the length h_default_seg32 picks), else 64-lane
+// segments; the shortest 64-lane V
 // segments that cover the column with 8 waves (measured faster than 16 shorter
 // ones: fewer carries to compose, more workgroups per CU), else with up to 16
 // waves -- except that the floating-point volumes then take two 32-lane
@@ -224,7 +225,7 @@ Split v_split_plan(int H, const Plan& pl) {
 // V kernels would need more than 64 VGPRs for two workgroups per CU).
 Plan default_plan(const zdt_params* p) {
   Plan pl{};
-  if (const int s32 = h_full_seg32(p->width)) {
+  if (const int s32 = h_default_seg32(p->width)) {
     pl.h_lanes = 32;
     pl.h_seg = s32;
   } else {

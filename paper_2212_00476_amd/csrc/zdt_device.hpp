@@ -68,8 +68,12 @@ template <>
 struct Elem<float> {
   static __device__ __forceinline__ float load(const float* p) { return *p; }
   static __device__ __forceinline__ void store(float* p, float v) { *p = v; }
+  static __device__ __forceinline__ uint32_t braw(rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0);
+  }
+  static __device__ __forceinline__ float decode(uint32_t u) { return __uint_as_float(u); }
   static __device__ __forceinline__ float bload(rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+    return decode(braw(r, voff, soff));
   }
   static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t voff, uint32_t soff, float v) {
     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, (int)soff, 0);
@@ -79,9 +83,14 @@ template <>
 struct Elem<_Float16> {
   static __device__ __forceinline__ float load(const _Float16* p) { return (float)*p; }
   static __device__ __forceinline__ void store(_Float16* p, float v) { *p = (_Float16)v; }
+  static __device__ __forceinline__ uint32_t braw(rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
+  }
+  static __device__ __forceinline__ float decode(uint32_t u) {
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)u);
+  }
   static __device__ __forceinline__ float bload(rsrc_t r, uint32_t voff, uint32_t soff) {
-    const unsigned short u = __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
-    return (float)__builtin_bit_cast(_Float16, u);
+    return decode(braw(r, voff, soff));
   }
   static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t voff, uint32_t soff, float v) {
     __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)v), r, (int)voff, (int)soff,
@@ -90,6 +99,10 @@ struct Elem<_Float16> {
 };
 template <>
 struct Elem<f16x> {
+  static __device__ __forceinline__ uint32_t braw(rsrc_t r, uint32_t voff, uint32_t soff) {
+    return Elem<_Float16>::braw(r, voff, soff);
+  }
+  static __device__ __forceinline__ float decode(uint32_t u) { return Elem<_Float16>::decode(u); }
   static __device__ __forceinline__ float bload(rsrc_t r, uint32_t voff, uint32_t soff) {
     return Elem<_Float16>::bload(r, voff, soff);
   }
@@ -103,9 +116,12 @@ struct Elem<bf16> {
   static __device__ __forceinline__ uint16_t encode(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
   static __device__ __forceinline__ float load(const bf16* p) { return __uint_as_float((uint32_t)p->bits << 16); }
   static __device__ __forceinline__ void store(bf16* p, float v) { p->bits = encode(v); }
+  static __device__ __forceinline__ uint32_t braw(rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
+  }
+  static __device__ __forceinline__ float decode(uint32_t u) { return __uint_as_float(u << 16); }
   static __device__ __forceinline__ float bload(rsrc_t r, uint32_t voff, uint32_t soff) {
-    const unsigned short u = __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
-    return __uint_as_float((uint32_t)u << 16);
+    return decode(braw(r, voff, soff));
   }
   static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t voff, uint32_t soff, float v) {
     __builtin_amdgcn_raw_buffer_store_b16(encode(v), r, (int)voff, (int)soff, 0);
@@ -152,8 +168,12 @@ __device__ __forceinline__ int i8_decode(uint32_t c) {
 template <>
 struct Elem<i16v> {
   static __device__ __forceinline__ float load(const i16v* p) { return (float)p->v; }
+  static __device__ __forceinline__ uint32_t braw(rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
+  }
+  static __device__ __forceinline__ float decode(uint32_t u) { return (float)(short)(unsigned short)u; }
   static __device__ __forceinline__ float bload(rsrc_t r, uint32_t voff, uint32_t soff) {
-    return (float)(short)__builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
+    return decode(braw(r, voff, soff));
   }
   static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t voff, uint32_t soff, float v) {
     __builtin_amdgcn_raw_buffer_store_b16((unsigned short)sat16(v), r, (int)voff, (int)soff, 0);
@@ -163,8 +183,12 @@ struct Elem<i16v> {
 template <>
 struct Elem<i8c> {
   static __device__ __forceinline__ float load(const i8c* p) { return (float)i8_decode(p->c); }
+  static __device__ __forceinline__ uint32_t braw(rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_amdgcn_raw_buffer_load_b8(r, (int)voff, (int)soff, 0);
+  }
+  static __device__ __forceinline__ float decode(uint32_t u) { return (float)i8_decode(u & 0xFFu); }
   static __device__ __forceinline__ float bload(rsrc_t r, uint32_t voff, uint32_t soff) {
-    return (float)i8_decode(__builtin_amdgcn_raw_buffer_load_b8(r, (int)voff, (int)soff, 0));
+    return decode(braw(r, voff, soff));
   }
   static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t voff, uint32_t soff, float v) {
     __builtin_amdgcn_raw_buffer_store_b8((unsigned char)i8_encode(sat16(v)), r, (int)voff, (int)soff, 0);
@@ -1150,11 +1174,14 @@ __device__ __forceinline__ void bfly_stage(uint32_t (&r)[N], int n, int lane) {
 // workgroups of a 1080-row column share a CU (without the bound the 16-bit
 // loads and their FP32 values are both kept live and one workgroup fills the
 // CU); so are the gain-scaled FP16 U/D pairs with 64-lane segments of up to 48
-// rows (four 8-wave workgroups per CU instead of three).  The integer volumes
-// keep the default: under the bound their codecs spill.
+// rows (four 8-wave workgroups per CU instead of three).  The integer
+// volumes' 64-lane pairs of up to 48 rows take 8 waves, 6 with the WTA (three
+// workgroups per CU instead of two; 80 VGPRs and a 16-byte spill, measured
+// 6-10 % faster); their 32-lane pairs keep the default (under the bound their
+// codecs spill).
 template <int SEG, int LPS, bool WTA, typename T>
 constexpr int v_waves_per_eu() {
-  if constexpr (is_int_vol<T>()) return 4;
+  if constexpr (is_int_vol<T>()) return (LPS == 64 && SEG <= 48) ? (WTA ? 6 : 8) : 4;
   if constexpr (LPS == 32 && SEG <= 36) return 8;
   return (LPS == 64 && SEG <= 48 && !WTA && std::is_same<T, f16x>::value) ? 8 : 4;
 }
@@ -1242,18 +1269,13 @@ __global__ __launch_bounds__(1024, (v_waves_per_eu<SEG, LPS, WTA, T>())) void vp
     return (uint32_t)k * rowbytes;
   };
 
-  // Scaled FP16 values are loaded as raw bits and converted in loop A, so
-  // each 16-bit value's register is free once its FP32 value exists (loaded
-  // and converted at once, both sets were live together and the 64-VGPR
-  // bound of 36-row segments spilled).
+  // Values are loaded as raw bits and decoded in loop A, so each loaded
+  // value's register is free once its FP32 value exists (loaded and decoded
+  // at once, both sets were live together and the 64-VGPR bound of 36-row
+  // segments spilled).
   float c[SEG];
 #pragma unroll
-  for (int k = 0; k < SEG; ++k) {
-    if constexpr (scaled)
-      c[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b16(vrs, (int)voff, (int)step_off(k), 0));
-    else
-      c[k] = Elem<T>::bload(vrs, voff, step_off(k));
-  }
+  for (int k = 0; k < SEG; ++k) c[k] = __uint_as_float(Elem<T>::braw(vrs, voff, step_off(k)));
   __builtin_amdgcn_sched_barrier(0);
   // ---- loop A: carry-free U pass (decoding scaled FP16 values on the way;
   // Int16's first sweep subtracts the stored R2L output's d = 0 slice first)
@@ -1264,8 +1286,8 @@ __global__ __launch_bounds__(1024, (v_waves_per_eu<SEG, LPS, WTA, T>())) void vp
   for (int k = 0; k < SEG; ++k) {
     const bool in = k < len;
     const float w = wp[k];
-    if constexpr (scaled)
-      c[k] = (float)__builtin_bit_cast(_Float16, (unsigned short)__float_as_uint(c[k])) * si[k];
+    c[k] = Elem<T>::decode(__float_as_uint(c[k]));
+    if constexpr (scaled) c[k] *= si[k];
     if constexpr (kInt)
       if (sub_ref) c[k] -= rf[k];
     ell = in ? fmaf(w, ell, c[k]) : ell;

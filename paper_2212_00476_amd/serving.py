@@ -25,6 +25,10 @@ The paper solves one pair at a time without streams; this module is the
 serving layer around its hot path.  The scheduler is plain host logic
 (``Scheduler``, ``serve``) driven by an executor; ``GpuExecutor`` runs it on
 the device and can check every result against the same pair solved alone.
+Latency is reported end to end (arrival on the host to the disparities in
+pinned host memory, uploads and downloads included) and device-only (the
+kernels of the batch a request was solved in, timed with events on its lane's
+stream).
 
     python -m paper_2212_00476_amd.serving --rate 300 --duration 60
 """
@@ -68,6 +72,7 @@ class Request:
     t_start: float = math.nan
     t_done: float = math.nan
     ok: bool | None = None   # result equal to the pair solved alone (when checked)
+    device_ms: float = math.nan   # device time of the batch it was solved in (kernels only)
 
     @property
     def latency(self):
@@ -261,11 +266,19 @@ def summarize(reqs, duration=None):
            "p50_ms": round(float(np.percentile(lat, 50)), 3) if len(lat) else None,
            "p99_ms": round(float(np.percentile(lat, 99)), 3) if len(lat) else None,
            "checked": sum(r.ok is not None for r in done), "mismatched": sum(r.ok is False for r in done)}
+    dev = np.array([r.device_ms for r in done if not math.isnan(r.device_ms)])
+    if len(dev):
+        out["device_p50_ms"] = round(float(np.percentile(dev, 50)), 3)
+        out["device_p99_ms"] = round(float(np.percentile(dev, 99)), 3)
     per = {}
     for s in sorted({r.shape for r in done}):
         ls = np.array([r.latency for r in done if r.shape == s]) * 1e3
         per[s] = {"n": int(len(ls)), "p50_ms": round(float(np.percentile(ls, 50)), 3),
                   "p99_ms": round(float(np.percentile(ls, 99)), 3)}
+        ds = np.array([r.device_ms for r in done if r.shape == s and not math.isnan(r.device_ms)])
+        if len(ds):
+            per[s]["device_p50_ms"] = round(float(np.percentile(ds, 50)), 3)
+            per[s]["device_p99_ms"] = round(float(np.percentile(ds, 99)), 3)
     out["per_shape"] = per
     return out
 
@@ -281,7 +294,9 @@ class _Lane:
     vols: list
     wss: list
     jobs: list
-    event: object
+    event: object           # completion of the last launch (after the download)
+    solve0: object          # timing events around the batch's kernels
+    solve1: object
     graphs: dict = field(default_factory=dict)
 
 
@@ -351,7 +366,8 @@ class GpuExecutor:
         jobs = [(p, left[i], right[i], disp[i], vols[i], wss[i]) for i in range(cap)]
         host_out = torch.empty((cap, sh.H, sh.W), dtype=torch.int32).pin_memory()
         self.lanes[lane_id] = _Lane(sh, torch.cuda.Stream(device=self.dev), left, right, disp, host_out, vols, wss,
-                                    jobs, torch.cuda.Event())
+                                    jobs, torch.cuda.Event(), torch.cuda.Event(enable_timing=True),
+                                    torch.cuda.Event(enable_timing=True))
 
     def destroy_lane(self, lane_id):
         lane = self.lanes.pop(lane_id)
@@ -380,6 +396,7 @@ class GpuExecutor:
                 src_l, src_r = self.pinned[r.shape][r.pair]
                 lane.left[k].copy_(src_l, non_blocking=True)
                 lane.right[k].copy_(src_r, non_blocking=True)
+            lane.solve0.record(lane.stream)
             if not self.use_graphs:
                 self.lib.stereo_solve_batch(lane.jobs[:n], stream=lane.stream)
             elif n in lane.graphs:
@@ -387,6 +404,7 @@ class GpuExecutor:
             else:   # capturing runs the batch once, eagerly, before recording it
                 lane.graphs[n] = self.lib.Graph(lane.jobs[:n], lane.stream)
                 self.graph_captures += 1
+            lane.solve1.record(lane.stream)
             lane.host_out[:n].copy_(lane.disp[:n], non_blocking=True)
             lane.event.record(lane.stream)
 
@@ -394,9 +412,12 @@ class GpuExecutor:
         return self.lanes[lane_id].event.query()
 
     def finish(self, lane_id, batch):
+        lane = self.lanes[lane_id]
+        dev_ms = lane.solve0.elapsed_time(lane.solve1)
+        for r in batch:
+            r.device_ms = dev_ms
         if not self.check:
             return
-        lane = self.lanes[lane_id]
         for k, r in enumerate(batch):
             r.ok = bool(np.array_equal(lane.host_out[k].numpy(), self.alone[r.shape][r.pair]))
 

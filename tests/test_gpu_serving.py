@@ -37,6 +37,9 @@ def _check_all(reqs):
     assert st["checked"] == len(reqs) and st["mismatched"] == 0
     assert all(r.t_arrive <= r.t_start <= r.t_done for r in reqs)
     assert all(not math.isnan(r.latency) for r in reqs)
+    # device-only time: positive, and within the end-to-end latency
+    assert all(0.0 < r.device_ms <= 1e3 * r.latency for r in reqs)
+    assert st["device_p50_ms"] <= st["p50_ms"] and st["device_p99_ms"] <= st["p99_ms"]
     return st
 
 

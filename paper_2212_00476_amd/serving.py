@@ -253,8 +253,11 @@ def serve(requests, scheduler, executor, clock=time.perf_counter, sleep=time.sle
             progress(now, done)
             next_note += 10.0
         if not progressed:
+            # poll while a lane runs or a request is due within a millisecond
+            # (a timed sleep wakes up to ~0.3 ms late, which small pairs would
+            # see in full); otherwise wake a little before the next arrival
             nxt = reqs[i].t_arrive - (clock() - t0) if i < len(reqs) else 0.0
-            sleep(min(max(nxt, 0.0), 2e-4) if scheduler.busy_lanes() or nxt > 0 else 0.0)
+            sleep(0.0 if scheduler.busy_lanes() or nxt < 1e-3 else nxt - 5e-4)
     return reqs
 
 

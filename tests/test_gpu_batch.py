@@ -115,6 +115,18 @@ def test_batch_is_ordered_on_the_callers_stream():
         assert torch.equal(got[i], want[i]), i
 
 
+def test_batch_on_the_null_stream():
+    """The NULL (legacy default) stream: the batch forks from it and joins back,
+    so a device synchronization sees every result."""
+    jobs = [Job(*m, seed=140 + i) for i, m in enumerate(MIX[:4])]
+    torch.cuda.synchronize()
+    zdt.stereo_solve_batch([j.tuple() for j in jobs], stream=0)
+    torch.cuda.synchronize()
+    got = [j.disp.clone() for j in jobs]
+    for i, j in enumerate(jobs):
+        assert torch.equal(got[i], j.solve_alone()), i
+
+
 def test_batches_from_two_threads():
     """Two host threads submit batches on their own streams at once; each job
     still equals its pair solved alone."""

@@ -141,8 +141,10 @@ def cpu_baseline(left, right, threads, one_core_slices):
 
 def accuracy_vs_oracle(torch, zdt, L, Rt, pr, disps, cagg, threads):
     """Every form against the FP64 oracle at 1280x384, D = 128 (the oracle's
-    own aggregated volume from the CPU-baseline run): disparity mismatch; the
-    raw cost volume's max |d cost| in FP32 / FP16 / BF16 (every element); the
+    own aggregated volume from the CPU-baseline run): disparity mismatch over
+    all pixels and over the border-free region (x >= D - 1 + r, x < W - r,
+    r <= y < H - r: no window or target column is clamped there); the raw cost
+    volume's max |d cost| in FP32 / FP16 / BF16 (every element); the
     canonical gap G = C - min_d C of the aggregated volume relative to max_d C
     -- FP32 and BF16 from dt_aggregate (divided by its reported scale), FP16
     from stereo_solve's working volume after its last H pair (decoded with its
@@ -153,8 +155,11 @@ def accuracy_vs_oracle(torch, zdt, L, Rt, pr, disps, cagg, threads):
     import oracle
     out = {}
     o_disp = np.argmin(cagg, axis=2)
+    inner = (slice(R, H - R), slice(D - 1 + R, W - R))
     for name, disp in disps.items():
-        out[name] = {"disp_mismatch_pct": round(100.0 * float((disp.cpu().numpy() != o_disp).mean()), 5)}
+        bad = disp.cpu().numpy() != o_disp
+        out[name] = {"disp_mismatch_pct": round(100.0 * float(bad.mean()), 5),
+                     "disp_mismatch_interior_pct": round(100.0 * float(bad[inner].mean()), 5)}
 
     def slices(fn):
         with ThreadPoolExecutor(max_workers=threads) as ex:

@@ -104,6 +104,49 @@ def time_steps(fn, steps, warmup, torch):
     return s.elapsed_time(e) / steps
 
 
+def step_spread(fn, n, torch):
+    """p10 / p50 / p90 (ms) of n solves, each timed alone with events on the
+    current stream."""
+    import numpy as np
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for a, b in evs:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    t = np.array([a.elapsed_time(b) for a, b in evs])
+    return {"p10": round(float(np.percentile(t, 10)), 5), "p50": round(float(np.percentile(t, 50)), 5),
+            "p90": round(float(np.percentile(t, 90)), 5), "runs": n}
+
+
+def graph_replay_ms(torch, zdt, solver, L, Rt, disp, steps, warmup):
+    """One solve captured by the library (zdt_graph_create) and replayed."""
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = zdt.Graph([(solver.p, L, Rt, disp, solver.vol, solver.ws)], s)
+    with torch.cuda.stream(s):
+        ms = time_steps(lambda: g.launch(s), steps, warmup, torch)
+    g.close()
+    return ms
+
+
+def transfer_times(torch, pr, dev, steps):
+    """Upload of the two images from pinned host memory and download of the
+    disparities to it (ms each), timed with events around the copies."""
+    hl = torch.from_numpy(pr.left).pin_memory()
+    hr = torch.from_numpy(pr.right).pin_memory()
+    dl, dr = torch.empty_like(hl, device=dev), torch.empty_like(hr, device=dev)
+    dd = torch.zeros(pr.left.shape, dtype=torch.int32, device=dev)
+    hd = torch.empty(pr.left.shape, dtype=torch.int32).pin_memory()
+
+    def up():
+        dl.copy_(hl, non_blocking=True)
+        dr.copy_(hr, non_blocking=True)
+    h2d = time_steps(up, steps, 3, torch)
+    d2h = time_steps(lambda: hd.copy_(dd, non_blocking=True), steps, 3, torch)
+    return {"h2d_images_ms": round(h2d, 5), "d2h_disparities_ms": round(d2h, 5)}
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -130,11 +173,19 @@ def cpu_baseline(left, right, threads, one_core_slices):
     t1 = time.perf_counter()
     oracle.solve_slices(left, right, R, ds1, SIGMA_S, SIGMA_R, ITERS, threads=1)
     dt1 = time.perf_counter() - t1
+    # the 320x96, D = 32 bands pair of the smallest configuration, one thread
+    from paper_2212_00476_amd import scenes
+    p0 = scenes.bands_pair()
+    t2 = time.perf_counter()
+    oracle.stereo_solve(p0.left, p0.right, 32, R, SIGMA_S, SIGMA_R, ITERS)
+    dt2 = time.perf_counter() - t2
     rec = {"value": round(W * H * D / dt / 1e9, 6), "unit": "Gcost-evals/s", "cores": threads, "kind": "oracle",
            "sample": "all %d disparity slices of the 1280x384 pair (cost + 3-sweep DT per slice, FP64), %.2f s "
                      "wall on %d threads" % (D, dt, threads),
            "single_core": {"value": round(W * H * len(ds1) / dt1 / 1e9, 6), "unit": "Gcost-evals/s", "cores": 1,
                            "sample": "%d of %d slices, %.2f s on one thread" % (len(ds1), D, dt1)},
+           "bands_320x96_d32": {"value": round(320 * 96 * 32 / dt2 / 1e9, 6), "unit": "Gcost-evals/s", "cores": 1,
+                                "sample": "the whole 320x96, D = 32 pair, %.2f s on one thread" % dt2},
            "nproc": os.cpu_count(), "cpu_model": cpu_model()}
     return rec, np.ascontiguousarray(np.moveaxis(c, 0, 2))
 
@@ -381,7 +432,10 @@ def main():
         ms = time_steps(lambda: solver(L, Rt, disp), args.steps, args.warmup, torch)
         forms[name] = {"ms_per_step": round(ms, 5), "gcost_evals_per_s": round(nvol / (ms * 1e-3) / 1e9, 3),
                        "fps": round(1000.0 / ms, 1), "d1_error_pct": d1_error_pct(disp, pr),
-                       "b_ref_frac": round(b_ref(sz, ITERS) / (ms * 1e-3) / (PEAK_HBM_GBS * 1e9), 4)}
+                       "b_ref_frac": round(b_ref(sz, ITERS) / (ms * 1e-3) / (PEAK_HBM_GBS * 1e9), 4),
+                       "step_ms": step_spread(lambda: solver(L, Rt, disp), 100, torch),
+                       "graph_replay_ms_per_step": round(graph_replay_ms(torch, zdt, solver, L, Rt, disp, args.steps,
+                                                                         args.warmup), 5)}
 
     # the paper's own system parameters: 3x3 window, one sweep, sigma_s = 5,
     # sigma_r = 52 on 0..255 (the configuration of its 32 fps Jetson TX2 figure)
@@ -478,6 +532,9 @@ def main():
     roofline = roofline_of(kt, 4, "f32", (W, H, D), "", mall)
     roofline_f16 = roofline_of(kt16, 2, "f16", (W, H, D), "", mall)
     copy_gbs = copy_bandwidth(torch, dev)
+    transfers = transfer_times(torch, pr, dev, args.steps)
+    transfers["pcie_inclusive_ms_per_pair_f32"] = round(forms["f32"]["ms_per_step"] + transfers["h2d_images_ms"] +
+                                                        transfers["d2h_disparities_ms"], 5)
     large = None if args.no_large else bench_out_of_cache(torch, zdt, dev, max(5, args.steps // 20), 2)
 
     batch = None if args.no_batch else bench_batch(torch, zdt)
@@ -501,7 +558,7 @@ def main():
         "fps": f32["fps"], "forms": forms, "kernels_f32": kernels, "kernels_f16": kernels_f16,
         "kernels_bf16": kernels_bf16, "kernels_sgm_s1": kernels_sgm,
         "kernels_sgm_s1_f16": kernels_sgm_f16, "roofline": roofline, "roofline_f16": roofline_f16,
-        "copy_GBps": copy_gbs, "out_of_cache": large, "cpu_baseline": cpu, "accuracy_vs_oracle": accuracy,
+        "copy_GBps": copy_gbs, "transfers": transfers, "out_of_cache": large, "cpu_baseline": cpu, "accuracy_vs_oracle": accuracy,
         "p99_ms_served": served["poisson"]["p99_ms"] if served else None,
         "batch": batch, "serving": served,
         "window_sweep_cost_ms": sweep,
